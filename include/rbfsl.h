@@ -1,0 +1,156 @@
+/*
+ * rbfsl.h -- C ABI of the MI355X (gfx950) local-stencil RBF semi-Lagrangian
+ * transport library.
+ *
+ * The method is the local RBF interpolation scheme of Shankar & Wright,
+ * "Mesh-free semi-Lagrangian methods for transport on a sphere using radial
+ * basis functions" (arXiv:1804.01609):
+ *   - Algorithm 1 (Section 3): each step traces every Eulerian node x_j back
+ *     to its departure point xi_j and sets q^{m+1}_j = s(xi_j);
+ *   - Section 3.2: the departure point solves the trajectory ODE (eq. sl_ode)
+ *     backward over one step, here with RK4 and an orthogonal projection onto
+ *     the sphere at every stage;
+ *   - Sections 2.2 and 3.3.2: s is the augmented local interpolant (eq.
+ *     rbf_poly) on an n-node stencil, with PHS phi(r) = r^(2k+1) and the
+ *     spherical harmonics of degree <= L (Section 2.4), whose coefficients
+ *     solve the saddle-point system (eq. rbf_poly_linsys) by LU with partial
+ *     pivoting.
+ *
+ * Every step runs on the GPU in hand-written HIP kernels; the host only
+ * evaluates the time-dependent coefficients of the velocity field (cosines and
+ * sines of the stage times) and enqueues work.
+ *
+ * Conventions for every function below:
+ *   - all return an int status (RBFSL_OK or a negative RBFSL_E_* code) unless
+ *     stated; none throws, aborts or returns memory the caller must free;
+ *   - arrays are plain pointers; a flag `*_on_device` says whether a pointer
+ *     is device memory (HIP/torch allocation on the context's device) or host
+ *     memory; inputs are copied, the caller keeps ownership;
+ *   - work is enqueued on the context's HIP stream (NULL = the default
+ *     stream); functions that return data to the caller synchronise that
+ *     stream first;
+ *   - a context is used by one host thread at a time; different contexts are
+ *     independent.
+ */
+#ifndef RBFSL_H
+#define RBFSL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rbfsl_ctx rbfsl_ctx; /* opaque; owns all of its device buffers */
+
+enum {
+    RBFSL_OK = 0,
+    RBFSL_E_INVAL = -1,     /* invalid argument or parameter combination */
+    RBFSL_E_NOMEM = -2,     /* a device or host allocation failed */
+    RBFSL_E_DEVICE = -3,    /* a HIP runtime call failed */
+    RBFSL_E_SINGULAR = -4,  /* a stencil system had a zero pivot (e.g. duplicate nodes) */
+    RBFSL_E_NONFINITE = -5, /* a stencil produced non-finite weights */
+    RBFSL_E_STATE = -6,     /* call not valid in the current state (e.g. q not set) */
+    RBFSL_E_SEARCH = -7     /* the neighbour search could not bound a stencil */
+};
+
+/* Velocity fields u(x,t) (tangent to the sphere, divergence free).
+ * vel[0] = T (period), vel[1..3] = unit axis a, vel[4] = amplitude kappa.
+ *   ZERO:       u = 0
+ *   SOLID_BODY: u = (2 pi/T) a x x                       (Section 4.1)
+ *   DEFORM:     u = x x grad psi + (2 pi/T) a x x with
+ *               psi = kappa cos(pi t/T) psi0(R(t)^T x), psi0 = xyz + z^2 x/2,
+ *               R(t) the rotation about a by 2 pi t/T; the flow reverses and
+ *               every parcel returns to its start at t = T. */
+enum { RBFSL_VEL_ZERO = 0, RBFSL_VEL_SOLID_BODY = 1, RBFSL_VEL_DEFORM = 2 };
+
+typedef struct {
+    int32_t n;            /* stencil size, 1 <= n <= N                                    */
+    int32_t L;            /* harmonic degree; -1 selects L = floor((sqrt(n)-1)/2) (Sec 2.4) */
+    int32_t k;            /* PHS order, phi = r^(2k+1), 0 <= k <= L; -1 selects k = L      */
+    int32_t stencil_mode; /* 0: n nearest nodes of xi_j, centred at xi_j;
+                             1: the paper's centre-point stencils: the n nearest nodes
+                                of the node nearest to xi_j (Section 3.3.2)            */
+    int32_t velocity_id;  /* RBFSL_VEL_*                                                  */
+    int32_t n_tracers;    /* number of fields sharing each step's weights, >= 1           */
+    double vel[8];        /* velocity parameters, see above                               */
+    double dt;            /* time step, > 0                                               */
+    double t0;            /* time of step 0                                               */
+} rbfsl_params;
+
+/* Create a transport context.
+ * nodes_xyz: N x 3 row-major (x, y, z) of nodes on the unit sphere (copied).
+ * Builds the spatial hash of the nodes (and, in stencil_mode 1, every node's
+ * stencil) on the device.  (n + (L+1)^2) must not exceed rbfsl_max_system().
+ * On failure *out is NULL. */
+int rbfsl_create(const double *nodes_xyz, int64_t N, int nodes_on_device,
+                 const rbfsl_params *p, void *hip_stream, rbfsl_ctx **out);
+
+/* Set q^m (n_tracers x N row-major, copied).  Does not change the step index. */
+int rbfsl_set_q(rbfsl_ctx *ctx, const double *q, int on_device);
+
+/* One step q^m -> q^{m+1}.  Synchronises and commits only if every stencil
+ * solved: on RBFSL_E_SINGULAR / _NONFINITE / _SEARCH the state stays at m. */
+int rbfsl_step(rbfsl_ctx *ctx);
+
+/* nsteps steps, enqueued without host synchronisation between them; one
+ * synchronisation at the end.  If step f fails, later steps do nothing and the
+ * state is left at step f (q^f), with the failure code returned. */
+int rbfsl_run(rbfsl_ctx *ctx, int64_t nsteps);
+
+/* Copy q^m out (n_tracers x N).  Synchronises. */
+int rbfsl_get_q(rbfsl_ctx *ctx, double *out, int on_device);
+
+/* Current step index m and time t0 + m dt. */
+int rbfsl_get_state(const rbfsl_ctx *ctx, int64_t *step, double *t);
+
+/* Number of stencils of the last step whose system was singular, non-finite,
+ * or whose neighbour search failed (each may be NULL). */
+int rbfsl_get_failures(const rbfsl_ctx *ctx, int64_t *singular, int64_t *nonfinite,
+                       int64_t *search);
+
+/* Measurement taps.  While profiling is enabled, every step records HIP
+ * events around each of its four phases on the context's stream; the
+ * accumulated device time per phase (ms: [0] trace, [1] stencil search,
+ * [2] assembly + elimination + back substitution, [3] apply) and the number of
+ * steps recorded are read (synchronising) by rbfsl_phase_times.  Enabling
+ * resets the totals. */
+int rbfsl_profile(rbfsl_ctx *ctx, int enable);
+int rbfsl_phase_times(rbfsl_ctx *ctx, double *ms, int64_t *steps);
+
+/* Parity taps: quantities of the last executed step (host outputs).
+ * departure: N x 3 departure points; stencils: N x n node indices in the
+ * order used (ascending (distance^2, index)); weights: N x n. */
+int rbfsl_debug_departure(rbfsl_ctx *ctx, double *xi);
+int rbfsl_debug_stencils(rbfsl_ctx *ctx, int32_t *idx);
+int rbfsl_debug_weights(rbfsl_ctx *ctx, double *w);
+
+/* Stateless exact neighbour search through the spatial hash: for each of Q
+ * query points (Q x 3), the n nodes with the smallest keys (d^2, index),
+ * d^2 = (dx*dx + dy*dy) + dz*dz, ascending.  idx: Q x n, d2: Q x n (may be
+ * NULL).  All arrays host or all device per `on_device`. */
+int rbfsl_knn(const double *nodes_xyz, int64_t N, const double *queries, int64_t Q, int32_t n,
+              int32_t *idx, double *d2, int on_device, void *hip_stream);
+
+/* Stateless batched weights for `count` stencils (Section 3.3.2 with the
+ * system of eq. rbf_poly_linsys): stencil t has node indices idx[t*n ..],
+ * centre centers[t], squared scale s2[t] and evaluation point evals[t]
+ * (all points x 3 row-major).  w: count x n, status: count (0, or the
+ * RBFSL_E_* code of that stencil; may be NULL). */
+int rbfsl_weights(const double *nodes_xyz, int64_t N, const int32_t *idx, const double *centers,
+                  const double *s2, const double *evals, int64_t count, int32_t n, int32_t L,
+                  int32_t k, double *w, int32_t *status, int on_device, void *hip_stream);
+
+/* Largest supported system size n + (L+1)^2. */
+int rbfsl_max_system(void);
+
+const char *rbfsl_strerror(int code);
+/* Message of the last failure on this context (owned by the context, valid
+ * until the next call on it). */
+const char *rbfsl_last_error(const rbfsl_ctx *ctx);
+void rbfsl_destroy(rbfsl_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

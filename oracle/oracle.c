@@ -75,6 +75,11 @@ int orc_threads(void) {
 /*                 u0(y) = y x grad psi0(y),  psi0 = y0 y1 y2 + y2^2 y0 / 2   */
 /* ------------------------------------------------------------------------ */
 
+/* libm cos and sin, each called on its own: a compiler may otherwise merge a
+ * cos/sin pair into one sincos() call, whose last bit can differ */
+static __attribute__((noinline)) double cos_of(double x) { return cos(x); }
+static __attribute__((noinline)) double sin_of(double x) { return sin(x); }
+
 typedef struct {
     double c;      /* time factor of the deformation part */
     double R[9];   /* row-major rotation matrix R(t) */
@@ -93,7 +98,7 @@ static void vel_coef_at(int vel_id, const double *vp, double t, vel_coef *vc) {
     vc->w[2] = Om * a[2];
     if (vel_id != VEL_DEFORM) return;
     double th = Om * t;
-    double ct = cos(th), st = sin(th);
+    double ct = cos_of(th), st = sin_of(th);
     double omc = 1.0 - ct;
     /* Rodrigues: R = cos I + sin [a]x + (1 - cos) a a^T, term by term */
     double K[9] = {0.0, -a[2], a[1],
@@ -104,7 +109,7 @@ static void vel_coef_at(int vel_id, const double *vp, double t, vel_coef *vc) {
             double d = (i == j) ? 1.0 : 0.0;
             vc->R[3 * i + j] = ((ct * d) + (st * K[3 * i + j])) + (omc * (a[i] * a[j]));
         }
-    vc->c = vp[4] * cos((M_PI * t) / T);
+    vc->c = vp[4] * cos_of((M_PI * t) / T);
 }
 
 static void cross(const double a[3], const double b[3], double o[3]) {

@@ -1,0 +1,263 @@
+"""Python binding of librbfsl (the MI355X local-stencil RBF semi-Lagrangian
+transport library): argument marshalling over the C ABI of include/rbfsl.h.
+
+Host arrays are numpy float64/int32; device arrays are torch CUDA (HIP)
+tensors, passed by pointer together with the current torch stream.  Every
+step of the method runs in the library's HIP kernels; there is no CPU path
+here, and loading fails loudly when the library has not been built.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librbfsl.so")
+
+RBFSL_OK = 0
+RBFSL_E_INVAL = -1
+RBFSL_E_NOMEM = -2
+RBFSL_E_DEVICE = -3
+RBFSL_E_SINGULAR = -4
+RBFSL_E_NONFINITE = -5
+RBFSL_E_STATE = -6
+RBFSL_E_SEARCH = -7
+
+VEL_ZERO, VEL_SOLID_BODY, VEL_DEFORM = 0, 1, 2
+
+EXPORTS = [
+    "rbfsl_create", "rbfsl_set_q", "rbfsl_step", "rbfsl_run", "rbfsl_get_q", "rbfsl_get_state",
+    "rbfsl_get_failures", "rbfsl_profile", "rbfsl_phase_times", "rbfsl_debug_departure", "rbfsl_debug_stencils", "rbfsl_debug_weights",
+    "rbfsl_knn", "rbfsl_weights", "rbfsl_max_system", "rbfsl_strerror", "rbfsl_last_error",
+    "rbfsl_destroy",
+]
+
+
+class RbfslError(RuntimeError):
+    def __init__(self, code, msg=""):
+        self.code = code
+        super().__init__(f"rbfsl error {code}: {msg}")
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32), ("L", ctypes.c_int32), ("k", ctypes.c_int32),
+        ("stencil_mode", ctypes.c_int32), ("velocity_id", ctypes.c_int32),
+        ("n_tracers", ctypes.c_int32), ("vel", ctypes.c_double * 8),
+        ("dt", ctypes.c_double), ("t0", ctypes.c_double),
+    ]
+
+
+_lib = None
+_P = ctypes.c_void_p
+
+
+def lib():
+    """Load librbfsl.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1804_01609_amd.build` (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        i64, i32 = ctypes.c_int64, ctypes.c_int32
+        L.rbfsl_create.argtypes = [_P, i64, ctypes.c_int, ctypes.POINTER(Params), _P, ctypes.POINTER(_P)]
+        L.rbfsl_set_q.argtypes = [_P, _P, ctypes.c_int]
+        L.rbfsl_step.argtypes = [_P]
+        L.rbfsl_run.argtypes = [_P, i64]
+        L.rbfsl_get_q.argtypes = [_P, _P, ctypes.c_int]
+        L.rbfsl_get_state.argtypes = [_P, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
+        L.rbfsl_get_failures.argtypes = [_P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.rbfsl_profile.argtypes = [_P, ctypes.c_int]
+        L.rbfsl_phase_times.argtypes = [_P, _P, ctypes.POINTER(i64)]
+        L.rbfsl_debug_departure.argtypes = [_P, _P]
+        L.rbfsl_debug_stencils.argtypes = [_P, _P]
+        L.rbfsl_debug_weights.argtypes = [_P, _P]
+        L.rbfsl_knn.argtypes = [_P, i64, _P, i64, i32, _P, _P, ctypes.c_int, _P]
+        L.rbfsl_weights.argtypes = [_P, i64, _P, _P, _P, _P, i64, i32, i32, i32, _P, _P, ctypes.c_int, _P]
+        L.rbfsl_max_system.restype = ctypes.c_int
+        L.rbfsl_strerror.restype = ctypes.c_char_p
+        L.rbfsl_strerror.argtypes = [ctypes.c_int]
+        L.rbfsl_last_error.restype = ctypes.c_char_p
+        L.rbfsl_last_error.argtypes = [_P]
+        L.rbfsl_destroy.argtypes = [_P]
+        L.rbfsl_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr(x, dtype):
+    """(pointer, on_device, keepalive) for a numpy array or torch tensor."""
+    if x is None:
+        return None, 0, None
+    if _is_torch(x):
+        import torch
+        tdt = torch.float64 if dtype == np.float64 else torch.int32
+        if x.dtype != tdt or not x.is_contiguous():
+            raise TypeError(f"expected a contiguous {tdt} tensor")
+        return ctypes.c_void_p(x.data_ptr()), (1 if x.is_cuda else 0), x
+    a = np.ascontiguousarray(x, dtype=dtype)
+    return a.ctypes.data_as(ctypes.c_void_p), 0, a
+
+
+def _stream(on_device):
+    if not on_device:
+        return None
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check(code, ctx=None):
+    if code != RBFSL_OK:
+        L = lib()
+        msg = L.rbfsl_strerror(code).decode()
+        if ctx:
+            extra = L.rbfsl_last_error(ctx).decode()
+            if extra:
+                msg += ": " + extra
+        raise RbfslError(code, msg)
+
+
+def make_params(n, L=-1, k=-1, stencil_mode=0, velocity_id=VEL_ZERO, vel=(), dt=0.1, t0=0.0,
+                n_tracers=1):
+    p = Params()
+    p.n, p.L, p.k = int(n), int(L), int(k)
+    p.stencil_mode, p.velocity_id, p.n_tracers = int(stencil_mode), int(velocity_id), int(n_tracers)
+    v = list(vel) + [0.0] * (8 - len(vel))
+    for i in range(8):
+        p.vel[i] = float(v[i])
+    p.dt, p.t0 = float(dt), float(t0)
+    return p
+
+
+class Transport:
+    """One transport problem on the GPU: nodes, parameters and the state q^m.
+
+    nodes: (N, 3) numpy array or CUDA tensor; q arrays are (n_tracers, N).
+    `stream` is a raw hipStream_t (int) or None for torch's current stream
+    when device tensors are used, else the default stream.
+    """
+
+    def __init__(self, nodes, params, stream=None):
+        L = lib()
+        ptr, dev, keep = _ptr(nodes, np.float64)
+        self.N = int(nodes.shape[0])
+        self.params = params
+        self.ntr = params.n_tracers
+        s = ctypes.c_void_p(stream) if stream is not None else _stream(dev)
+        self._ctx = _P()
+        code = L.rbfsl_create(ptr, self.N, dev, ctypes.byref(params), s, ctypes.byref(self._ctx))
+        if code != RBFSL_OK:
+            self._ctx = None
+            _check(code)
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().rbfsl_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_q(self, q):
+        ptr, dev, keep = _ptr(q, np.float64)
+        _check(lib().rbfsl_set_q(self._ctx, ptr, dev), self._ctx)
+
+    def step(self):
+        _check(lib().rbfsl_step(self._ctx), self._ctx)
+
+    def run(self, nsteps):
+        _check(lib().rbfsl_run(self._ctx, int(nsteps)), self._ctx)
+
+    def run_status(self, nsteps):
+        """run() returning the status code instead of raising."""
+        return lib().rbfsl_run(self._ctx, int(nsteps))
+
+    def get_q(self, out=None):
+        if out is None:
+            out = np.zeros((self.ntr, self.N))
+        ptr, dev, keep = _ptr(out, np.float64)
+        _check(lib().rbfsl_get_q(self._ctx, ptr, dev), self._ctx)
+        return out
+
+    def state(self):
+        m = ctypes.c_int64()
+        t = ctypes.c_double()
+        _check(lib().rbfsl_get_state(self._ctx, ctypes.byref(m), ctypes.byref(t)))
+        return m.value, t.value
+
+    def failures(self):
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().rbfsl_get_failures(self._ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def profile(self, enable=True):
+        _check(lib().rbfsl_profile(self._ctx, int(bool(enable))), self._ctx)
+
+    def phase_times(self):
+        """Accumulated device ms per phase (trace, search, solve, apply) and steps."""
+        ms = np.zeros(4)
+        st = ctypes.c_int64()
+        _check(lib().rbfsl_phase_times(self._ctx, ms.ctypes.data_as(_P), ctypes.byref(st)), self._ctx)
+        return ms, st.value
+
+    def departure(self):
+        xi = np.zeros((self.N, 3))
+        _check(lib().rbfsl_debug_departure(self._ctx, xi.ctypes.data_as(_P)), self._ctx)
+        return xi
+
+    def stencils(self):
+        S = np.zeros((self.N, self.params.n), dtype=np.int32)
+        _check(lib().rbfsl_debug_stencils(self._ctx, S.ctypes.data_as(_P)), self._ctx)
+        return S
+
+    def weights(self):
+        w = np.zeros((self.N, self.params.n))
+        _check(lib().rbfsl_debug_weights(self._ctx, w.ctypes.data_as(_P)), self._ctx)
+        return w
+
+
+def knn(nodes, queries, n):
+    """Exact n nearest nodes of every query (host numpy in, host numpy out)."""
+    nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+    queries = np.ascontiguousarray(queries, dtype=np.float64).reshape(-1, 3)
+    Q = queries.shape[0]
+    idx = np.zeros((Q, n), dtype=np.int32)
+    d2 = np.zeros((Q, n))
+    _check(lib().rbfsl_knn(nodes.ctypes.data_as(_P), nodes.shape[0], queries.ctypes.data_as(_P), Q,
+                           int(n), idx.ctypes.data_as(_P), d2.ctypes.data_as(_P), 0, None))
+    return idx, d2
+
+
+def weights(nodes, idx, centers, s2, evals, n, L, k):
+    """Batched stencil weights (host numpy in/out); returns (w, status)."""
+    nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+    idx = np.ascontiguousarray(idx, dtype=np.int32).reshape(-1, n)
+    count = idx.shape[0]
+    centers = np.ascontiguousarray(centers, dtype=np.float64).reshape(count, 3)
+    evals = np.ascontiguousarray(evals, dtype=np.float64).reshape(count, 3)
+    s2 = np.ascontiguousarray(s2, dtype=np.float64).reshape(count)
+    w = np.zeros((count, n))
+    st = np.zeros(count, dtype=np.int32)
+    _check(lib().rbfsl_weights(nodes.ctypes.data_as(_P), nodes.shape[0], idx.ctypes.data_as(_P),
+                               centers.ctypes.data_as(_P), s2.ctypes.data_as(_P),
+                               evals.ctypes.data_as(_P), count, int(n), int(L), int(k),
+                               w.ctypes.data_as(_P), st.ctypes.data_as(_P), 0, None))
+    return w, st
+
+
+def max_system():
+    return lib().rbfsl_max_system()

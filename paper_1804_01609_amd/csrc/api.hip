@@ -1,0 +1,589 @@
+// Host side of the C ABI declared in rbfsl.h: parameter validation, buffer
+// ownership, the per-step velocity coefficients (the only transcendental
+// functions evaluated anywhere: cos/sin of the stage times) and the enqueueing
+// of the step kernels (Algorithm 1: trace -> stencils -> weights -> apply).
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "rbfsl_impl.h"
+
+using namespace rbfsl;
+
+struct rbfsl_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    rbfsl_params p{};
+    int n = 0, L = 0, k = 0, M = 0, ntr = 1, mode = 0;
+    int64_t N = 0;
+    double *nx = nullptr, *ny = nullptr, *nz = nullptr;
+    Grid grid;
+    double *ex = nullptr, *ey = nullptr, *ez = nullptr;  // departure points
+    int32_t *S = nullptr;                                // stencils (mode 1: of every node)
+    double *s2 = nullptr;
+    int32_t *cidx = nullptr;                             // mode 1: nearest node of xi_j
+    double *w = nullptr;
+    double *q[2] = {nullptr, nullptr};
+    int cur = 0;
+    int *status = nullptr;
+    int64_t step = 0;
+    bool q_set = false, ran = false;
+    int64_t f_sing = 0, f_nonf = 0, f_search = 0;
+    // profiling: per-step events around the four phases
+    bool prof = false;
+    std::vector<hipEvent_t> ev;  // 5 per recorded step
+    int64_t ev_used = 0, prof_steps = 0;
+    double prof_ms[4] = {0, 0, 0, 0};
+    std::string err;
+};
+
+namespace {
+
+int fail(rbfsl_ctx *c, int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(rbfsl_ctx *c, int code, const char *fmt, ...) {
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return code;
+}
+
+#define HIP_TRY(ctx, call)                                                                   \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail((ctx), e_ == hipErrorOutOfMemory ? RBFSL_E_NOMEM : RBFSL_E_DEVICE,   \
+                        "%s: %s", #call, hipGetErrorString(e_));                             \
+    } while (0)
+
+// libm cos and sin, each called on its own (a merged sincos() call can differ
+// in the last bit)
+__attribute__((noinline)) double cos_of(double x) { return cos(x); }
+__attribute__((noinline)) double sin_of(double x) { return sin(x); }
+
+// velocity coefficients at time t (see rbfsl.h); evaluated term by term in a
+// fixed order
+void vel_coef_at(int vel_id, const double *vp, double t, VelCoef *vc) {
+    memset(vc, 0, sizeof(*vc));
+    vc->R[0] = 1.0;
+    vc->R[4] = 1.0;
+    vc->R[8] = 1.0;
+    if (vel_id == RBFSL_VEL_ZERO) return;
+    const double T = vp[0];
+    const double a[3] = {vp[1], vp[2], vp[3]};
+    const double Om = (2.0 * M_PI) / T;
+    for (int i = 0; i < 3; ++i) vc->w[i] = Om * a[i];
+    if (vel_id != RBFSL_VEL_DEFORM) return;
+    const double th = Om * t;
+    const double ct = cos_of(th), st = sin_of(th);
+    const double omc = 1.0 - ct;
+    const double K[9] = {0.0, -a[2], a[1], a[2], 0.0, -a[0], -a[1], a[0], 0.0};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const double d = (i == j) ? 1.0 : 0.0;
+            vc->R[3 * i + j] = ((ct * d) + (st * K[3 * i + j])) + (omc * (a[i] * a[j]));
+        }
+    vc->c = vp[4] * cos_of((M_PI * t) / T);
+}
+
+StepCoef step_coef(const rbfsl_params &p, int64_t m) {
+    StepCoef sc;
+    const double t1 = p.t0 + (double)(m + 1) * p.dt;
+    const double tm = p.t0 + (double)m * p.dt;
+    const double th = t1 - 0.5 * p.dt;
+    vel_coef_at(p.velocity_id, p.vel, t1, &sc.c1);
+    vel_coef_at(p.velocity_id, p.vel, th, &sc.ch);
+    vel_coef_at(p.velocity_id, p.vel, tm, &sc.c0);
+    sc.h = -p.dt;
+    sc.hh = 0.5 * sc.h;
+    sc.h6 = sc.h / 6.0;
+    sc.vel_id = p.velocity_id;
+    return sc;
+}
+
+__global__ void k_aos_to_soa(const double *aos, int64_t N, double *x, double *y, double *z) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    x[i] = aos[3 * i];
+    y[i] = aos[3 * i + 1];
+    z[i] = aos[3 * i + 2];
+}
+
+__global__ void k_soa_to_aos(const double *x, const double *y, const double *z, int64_t N, double *aos) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    aos[3 * i] = x[i];
+    aos[3 * i + 1] = y[i];
+    aos[3 * i + 2] = z[i];
+}
+
+__global__ void k_gather_rows(const int32_t *S, const int32_t *cidx, int64_t N, int n, int32_t *out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N * n) return;
+    int64_t j = i / n, a = i % n;
+    out[i] = S[(int64_t)cidx[j] * n + a];
+}
+
+// upload an N x 3 AoS array (host or device) as SoA device arrays
+hipError_t upload_points(const double *xyz, int64_t N, int on_device, double *x, double *y,
+                         double *z, hipStream_t s) {
+    if (N == 0) return hipSuccess;
+    double *tmp = nullptr;
+    hipError_t e = hipMalloc(&tmp, sizeof(double) * 3 * N);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(tmp, xyz, sizeof(double) * 3 * N,
+                       on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_aos_to_soa, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, tmp,
+                           N, x, y, z);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(tmp);
+    return e;
+}
+
+hipError_t download_points(const double *x, const double *y, const double *z, int64_t N,
+                           double *xyz_host, hipStream_t s) {
+    if (N == 0) return hipSuccess;
+    double *tmp = nullptr;
+    hipError_t e = hipMalloc(&tmp, sizeof(double) * 3 * N);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_soa_to_aos, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, x, y, z,
+                       N, tmp);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(xyz_host, tmp, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(tmp);
+    return e;
+}
+
+int paper_L(int n) {
+    int L = 0;
+    while ((2 * (L + 1) + 1) * (2 * (L + 1) + 1) <= n) ++L;
+    return L;
+}
+
+// validated (n, L, k) or an error message
+int resolve_nlk(int64_t N, int n, int L, int k, int *Lo, int *ko, char *msg, size_t msz) {
+    if (n < 1 || (int64_t)n > N) {
+        snprintf(msg, msz, "stencil size n=%d must be in [1, N=%lld]", n, (long long)N);
+        return RBFSL_E_INVAL;
+    }
+    if (L < 0) L = paper_L(n);
+    if (k < 0) k = L;
+    if (k > L) {
+        snprintf(msg, msz, "PHS order k=%d must not exceed the harmonic degree L=%d", k, L);
+        return RBFSL_E_INVAL;
+    }
+    if ((L + 1) * (L + 1) > n) {
+        snprintf(msg, msz, "n=%d nodes cannot determine the (L+1)^2=%d harmonics of degree L=%d", n,
+                 (L + 1) * (L + 1), L);
+        return RBFSL_E_INVAL;
+    }
+    const int M = n + (L + 1) * (L + 1);
+    if (solve_variant_capacity(M) == 0) {
+        snprintf(msg, msz, "system size n+(L+1)^2=%d exceeds the supported maximum %d", M, MAX_SYSTEM);
+        return RBFSL_E_INVAL;
+    }
+    *Lo = L;
+    *ko = k;
+    return RBFSL_OK;
+}
+
+void ctx_free(rbfsl_ctx *c) {
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    c->ev.clear();
+    void *bufs[] = {c->nx, c->ny, c->nz, c->ex, c->ey, c->ez, c->S, c->s2, c->cidx, c->w,
+                    c->q[0], c->q[1], c->status};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    grid_free(&c->grid);
+}
+
+int read_status(rbfsl_ctx *c, int st[ST_WORDS]) {
+    HIP_TRY(c, hipMemcpyAsync(st, c->status, sizeof(int) * ST_WORDS, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return RBFSL_OK;
+}
+
+int status_code(const int st[ST_WORDS]) {
+    if (st[ST_SEARCH]) return RBFSL_E_SEARCH;
+    if (st[ST_SINGULAR]) return RBFSL_E_SINGULAR;
+    if (st[ST_NONFINITE]) return RBFSL_E_NONFINITE;
+    return RBFSL_OK;
+}
+
+hipError_t prof_mark(rbfsl_ctx *c, int phase) {
+    if (!c->prof) return hipSuccess;
+    const int64_t need = c->ev_used + 1;
+    while ((int64_t)c->ev.size() < need) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        c->ev.push_back(e);
+    }
+    (void)phase;
+    return hipEventRecord(c->ev[c->ev_used++], c->stream);
+}
+
+// fold recorded events into the per-phase totals (after a synchronisation)
+void prof_collect(rbfsl_ctx *c) {
+    for (int64_t b = 0; b + 5 <= c->ev_used; b += 5) {
+        for (int ph = 0; ph < 4; ++ph) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, c->ev[b + ph], c->ev[b + ph + 1]) == hipSuccess) c->prof_ms[ph] += ms;
+        }
+        c->prof_steps += 1;
+    }
+    c->ev_used = 0;
+}
+
+hipError_t enqueue_step(rbfsl_ctx *c, int64_t m) {
+    const StepCoef sc = step_coef(c->p, m);
+    hipError_t e = prof_mark(c, 0);
+    if (e != hipSuccess) return e;
+    e = launch_trace(c->nx, c->ny, c->nz, c->N, sc, c->ex, c->ey, c->ez, c->status, m, c->stream);
+    if (e != hipSuccess) return e;
+    if ((e = prof_mark(c, 1)) != hipSuccess) return e;
+    if (c->mode == 0)
+        e = launch_knn(c->grid, c->N, c->ex, c->ey, c->ez, c->N, c->n, c->S, nullptr, c->s2, c->status, m, c->stream);
+    else
+        e = launch_knn(c->grid, c->N, c->ex, c->ey, c->ez, c->N, 1, c->cidx, nullptr, nullptr, c->status, m, c->stream);
+    if (e != hipSuccess) return e;
+    if ((e = prof_mark(c, 2)) != hipSuccess) return e;
+    SolveArgs a{};
+    a.nx = c->nx; a.ny = c->ny; a.nz = c->nz; a.N = c->N;
+    a.ex = c->ex; a.ey = c->ey; a.ez = c->ez;
+    if (c->mode == 1) {
+        a.cx = c->nx; a.cy = c->ny; a.cz = c->nz;
+        a.cidx = c->cidx;
+    }
+    a.S = c->S; a.s2 = c->s2;
+    a.count = c->N; a.n = c->n; a.L = c->L; a.k = c->k;
+    a.w = c->w; a.st_out = nullptr; a.status = c->status; a.step = m;
+    e = launch_solve(a, c->stream);
+    if (e != hipSuccess) return e;
+    if ((e = prof_mark(c, 3)) != hipSuccess) return e;
+    e = launch_apply(c->w, c->S, c->mode == 1 ? c->cidx : nullptr, c->N, c->n, c->ntr,
+                     c->q[c->cur], c->q[1 - c->cur], c->status, m, c->stream);
+    if (e != hipSuccess) return e;
+    return prof_mark(c, 4);
+}
+
+}  // namespace
+
+extern "C" {
+
+int rbfsl_max_system(void) { return MAX_SYSTEM; }
+
+const char *rbfsl_strerror(int code) {
+    switch (code) {
+        case RBFSL_OK: return "ok";
+        case RBFSL_E_INVAL: return "invalid argument";
+        case RBFSL_E_NOMEM: return "out of memory";
+        case RBFSL_E_DEVICE: return "HIP runtime error";
+        case RBFSL_E_SINGULAR: return "singular stencil system";
+        case RBFSL_E_NONFINITE: return "non-finite stencil weights";
+        case RBFSL_E_STATE: return "invalid state";
+        case RBFSL_E_SEARCH: return "neighbour search failed";
+        default: return "unknown status";
+    }
+}
+
+const char *rbfsl_last_error(const rbfsl_ctx *c) { return c ? c->err.c_str() : ""; }
+
+int rbfsl_create(const double *nodes_xyz, int64_t N, int nodes_on_device, const rbfsl_params *p,
+                 void *hip_stream, rbfsl_ctx **out) {
+    if (!out) return RBFSL_E_INVAL;
+    *out = nullptr;
+    if (!p || !nodes_xyz || N < 1 || N > 0x7fffffffLL) return RBFSL_E_INVAL;
+    if (!(p->dt > 0.0) || !isfinite(p->dt) || !isfinite(p->t0) || p->n_tracers < 1) return RBFSL_E_INVAL;
+    if (p->velocity_id < RBFSL_VEL_ZERO || p->velocity_id > RBFSL_VEL_DEFORM) return RBFSL_E_INVAL;
+    if (p->velocity_id != RBFSL_VEL_ZERO && (!(p->vel[0] != 0.0) || !isfinite(p->vel[0]))) return RBFSL_E_INVAL;
+    if (p->stencil_mode != 0 && p->stencil_mode != 1) return RBFSL_E_INVAL;
+    int L, k;
+    char msg[256];
+    if (resolve_nlk(N, p->n, p->L, p->k, &L, &k, msg, sizeof msg) != RBFSL_OK) return RBFSL_E_INVAL;
+    rbfsl_ctx *c = new (std::nothrow) rbfsl_ctx();
+    if (!c) return RBFSL_E_NOMEM;
+    c->p = *p;
+    c->p.L = L;
+    c->p.k = k;
+    c->n = p->n; c->L = L; c->k = k; c->M = p->n + (L + 1) * (L + 1);
+    c->ntr = p->n_tracers; c->mode = p->stencil_mode; c->N = N;
+    c->stream = (hipStream_t)hip_stream;
+    hipError_t e = hipGetDevice(&c->device);
+    const size_t d = sizeof(double);
+#define ALLOC(ptr, bytes) if (e == hipSuccess) e = hipMalloc(&(ptr), (bytes))
+    ALLOC(c->nx, d * N); ALLOC(c->ny, d * N); ALLOC(c->nz, d * N);
+    ALLOC(c->ex, d * N); ALLOC(c->ey, d * N); ALLOC(c->ez, d * N);
+    ALLOC(c->S, sizeof(int32_t) * N * c->n);
+    ALLOC(c->s2, d * N);
+    ALLOC(c->w, d * N * c->n);
+    ALLOC(c->q[0], d * N * c->ntr); ALLOC(c->q[1], d * N * c->ntr);
+    ALLOC(c->status, sizeof(int) * ST_WORDS);
+    if (c->mode == 1) ALLOC(c->cidx, sizeof(int32_t) * N);
+#undef ALLOC
+    if (e == hipSuccess) e = upload_points(nodes_xyz, N, nodes_on_device, c->nx, c->ny, c->nz, c->stream);
+    if (e == hipSuccess) e = grid_build(c->nx, c->ny, c->nz, N, c->n, &c->grid, c->stream);
+    if (e == hipSuccess) e = launch_status_reset(c->status, c->stream);
+    if (e == hipSuccess && c->mode == 1) {
+        // every node's own stencil, found once (the nodes do not move)
+        e = launch_knn(c->grid, N, c->nx, c->ny, c->nz, N, c->n, c->S, nullptr, c->s2, c->status, 0, c->stream);
+        int st[ST_WORDS];
+        if (e == hipSuccess) e = hipMemcpyAsync(st, c->status, sizeof st, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e == hipSuccess && st[ST_SEARCH]) {
+            ctx_free(c);
+            delete c;
+            return RBFSL_E_SEARCH;
+        }
+    }
+    if (e != hipSuccess) {
+        int code = (e == hipErrorOutOfMemory) ? RBFSL_E_NOMEM : RBFSL_E_DEVICE;
+        ctx_free(c);
+        delete c;
+        return code;
+    }
+    *out = c;
+    return RBFSL_OK;
+}
+
+int rbfsl_set_q(rbfsl_ctx *c, const double *q, int on_device) {
+    if (!c || !q) return RBFSL_E_INVAL;
+    HIP_TRY(c, hipMemcpyAsync(c->q[c->cur], q, sizeof(double) * c->N * c->ntr,
+                              on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->q_set = true;
+    return RBFSL_OK;
+}
+
+int rbfsl_run(rbfsl_ctx *c, int64_t nsteps) {
+    if (!c || nsteps < 0) return RBFSL_E_INVAL;
+    if (!c->q_set) return fail(c, RBFSL_E_STATE, "q has not been set");
+    if (nsteps == 0) return RBFSL_OK;
+    HIP_TRY(c, launch_status_reset(c->status, c->stream));
+    const int64_t m0 = c->step;
+    const int cur0 = c->cur;
+    for (int64_t m = m0; m < m0 + nsteps; ++m) {
+        c->cur = cur0 ^ (int)((m - m0) & 1);  // buffer holding q^m
+        hipError_t e = enqueue_step(c, m);
+        if (e != hipSuccess) {
+            (void)hipStreamSynchronize(c->stream);
+            c->cur = cur0;
+            return fail(c, RBFSL_E_DEVICE, "step %lld launch: %s", (long long)m, hipGetErrorString(e));
+        }
+    }
+    int st[ST_WORDS];
+    int r = read_status(c, st);
+    if (r != RBFSL_OK) {
+        c->cur = cur0;
+        return r;
+    }
+    prof_collect(c);
+    c->ran = true;
+    c->f_sing = st[ST_SINGULAR];
+    c->f_nonf = st[ST_NONFINITE];
+    c->f_search = st[ST_SEARCH];
+    if (st[ST_FAILSTEP] != NO_FAIL) {
+        // steps f, f+1, ... did nothing: the state is q^f
+        const int64_t f = st[ST_FAILSTEP];
+        c->cur = cur0 ^ (int)((f - m0) & 1);
+        c->step = f;
+        return fail(c, status_code(st), "step %lld: %d singular, %d non-finite, %d search failures",
+                    (long long)f, st[ST_SINGULAR], st[ST_NONFINITE], st[ST_SEARCH]);
+    }
+    c->cur = cur0 ^ (int)(nsteps & 1);
+    c->step = m0 + nsteps;
+    return RBFSL_OK;
+}
+
+int rbfsl_step(rbfsl_ctx *c) { return rbfsl_run(c, 1); }
+
+int rbfsl_get_q(rbfsl_ctx *c, double *out, int on_device) {
+    if (!c || !out) return RBFSL_E_INVAL;
+    if (!c->q_set) return fail(c, RBFSL_E_STATE, "q has not been set");
+    HIP_TRY(c, hipMemcpyAsync(out, c->q[c->cur], sizeof(double) * c->N * c->ntr,
+                              on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return RBFSL_OK;
+}
+
+int rbfsl_get_state(const rbfsl_ctx *c, int64_t *step, double *t) {
+    if (!c) return RBFSL_E_INVAL;
+    if (step) *step = c->step;
+    if (t) *t = c->p.t0 + (double)c->step * c->p.dt;
+    return RBFSL_OK;
+}
+
+int rbfsl_get_failures(const rbfsl_ctx *c, int64_t *singular, int64_t *nonfinite, int64_t *search) {
+    if (!c) return RBFSL_E_INVAL;
+    if (singular) *singular = c->f_sing;
+    if (nonfinite) *nonfinite = c->f_nonf;
+    if (search) *search = c->f_search;
+    return RBFSL_OK;
+}
+
+int rbfsl_profile(rbfsl_ctx *c, int enable) {
+    if (!c) return RBFSL_E_INVAL;
+    c->prof = enable != 0;
+    c->ev_used = 0;
+    c->prof_steps = 0;
+    for (double &v : c->prof_ms) v = 0.0;
+    return RBFSL_OK;
+}
+
+int rbfsl_phase_times(rbfsl_ctx *c, double *ms, int64_t *steps) {
+    if (!c || !ms) return RBFSL_E_INVAL;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    prof_collect(c);
+    for (int i = 0; i < 4; ++i) ms[i] = c->prof_ms[i];
+    if (steps) *steps = c->prof_steps;
+    return RBFSL_OK;
+}
+
+int rbfsl_debug_departure(rbfsl_ctx *c, double *xi) {
+    if (!c || !xi) return RBFSL_E_INVAL;
+    if (!c->ran) return fail(c, RBFSL_E_STATE, "no step has run");
+    HIP_TRY(c, download_points(c->ex, c->ey, c->ez, c->N, xi, c->stream));
+    return RBFSL_OK;
+}
+
+int rbfsl_debug_stencils(rbfsl_ctx *c, int32_t *idx) {
+    if (!c || !idx) return RBFSL_E_INVAL;
+    if (!c->ran) return fail(c, RBFSL_E_STATE, "no step has run");
+    const size_t bytes = sizeof(int32_t) * c->N * c->n;
+    if (c->mode == 0) {
+        HIP_TRY(c, hipMemcpyAsync(idx, c->S, bytes, hipMemcpyDeviceToHost, c->stream));
+    } else {
+        int32_t *tmp = nullptr;
+        HIP_TRY(c, hipMalloc(&tmp, bytes));
+        hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((c->N * c->n + 255) / 256)), dim3(256), 0,
+                           c->stream, c->S, c->cidx, c->N, c->n, tmp);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(idx, tmp, bytes, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        (void)hipFree(tmp);
+        if (e != hipSuccess) return fail(c, RBFSL_E_DEVICE, "stencil gather: %s", hipGetErrorString(e));
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return RBFSL_OK;
+}
+
+int rbfsl_debug_weights(rbfsl_ctx *c, double *w) {
+    if (!c || !w) return RBFSL_E_INVAL;
+    if (!c->ran) return fail(c, RBFSL_E_STATE, "no step has run");
+    HIP_TRY(c, hipMemcpyAsync(w, c->w, sizeof(double) * c->N * c->n, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return RBFSL_OK;
+}
+
+void rbfsl_destroy(rbfsl_ctx *c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    ctx_free(c);
+    delete c;
+}
+
+int rbfsl_knn(const double *nodes_xyz, int64_t N, const double *queries, int64_t Q, int32_t n,
+              int32_t *idx, double *d2, int on_device, void *hip_stream) {
+    if (!nodes_xyz || !queries || !idx || N < 1 || N > 0x7fffffffLL || Q < 0 || n < 1 || n > N ||
+        n > KNN_CAP)
+        return RBFSL_E_INVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const size_t d = sizeof(double);
+    double *nx = nullptr, *ny = nullptr, *nz = nullptr, *qx = nullptr, *qy = nullptr, *qz = nullptr, *dd = nullptr;
+    int32_t *ii = nullptr;
+    int *status = nullptr;
+    Grid g;
+    int code = RBFSL_OK;
+    hipError_t e = hipSuccess;
+#define ALLOC(ptr, bytes) if (e == hipSuccess) e = hipMalloc(&(ptr), (bytes))
+    ALLOC(nx, d * N); ALLOC(ny, d * N); ALLOC(nz, d * N);
+    ALLOC(qx, d * (Q + 1)); ALLOC(qy, d * (Q + 1)); ALLOC(qz, d * (Q + 1));
+    ALLOC(ii, sizeof(int32_t) * (Q * n + 1));
+    ALLOC(dd, d * (Q * n + 1));
+    ALLOC(status, sizeof(int) * ST_WORDS);
+#undef ALLOC
+    if (e == hipSuccess) e = upload_points(nodes_xyz, N, on_device, nx, ny, nz, s);
+    if (e == hipSuccess) e = upload_points(queries, Q, on_device, qx, qy, qz, s);
+    if (e == hipSuccess) e = grid_build(nx, ny, nz, N, n, &g, s);
+    if (e == hipSuccess) e = launch_status_reset(status, s);
+    if (e == hipSuccess) e = launch_knn(g, N, qx, qy, qz, Q, n, ii, dd, nullptr, status, 0, s);
+    int st[ST_WORDS] = {0, 0, 0, NO_FAIL};
+    if (e == hipSuccess) e = hipMemcpyAsync(st, status, sizeof st, hipMemcpyDeviceToHost, s);
+    const hipMemcpyKind out = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (e == hipSuccess && Q > 0) e = hipMemcpyAsync(idx, ii, sizeof(int32_t) * Q * n, out, s);
+    if (e == hipSuccess && Q > 0 && d2) e = hipMemcpyAsync(d2, dd, d * Q * n, out, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) code = (e == hipErrorOutOfMemory) ? RBFSL_E_NOMEM : RBFSL_E_DEVICE;
+    else if (st[ST_SEARCH]) code = RBFSL_E_SEARCH;
+    void *bufs[] = {nx, ny, nz, qx, qy, qz, ii, dd, status};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    grid_free(&g);
+    return code;
+}
+
+int rbfsl_weights(const double *nodes_xyz, int64_t N, const int32_t *idx, const double *centers,
+                  const double *s2, const double *evals, int64_t count, int32_t n, int32_t L,
+                  int32_t k, double *w, int32_t *status_out, int on_device, void *hip_stream) {
+    if (!nodes_xyz || !idx || !centers || !s2 || !evals || !w || N < 1 || count < 0) return RBFSL_E_INVAL;
+    int Lr, kr;
+    char msg[256];
+    if (resolve_nlk(N, n, L, k, &Lr, &kr, msg, sizeof msg) != RBFSL_OK) return RBFSL_E_INVAL;
+    if (count == 0) return RBFSL_OK;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const size_t d = sizeof(double);
+    const hipMemcpyKind in = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    double *nx = nullptr, *ny = nullptr, *nz = nullptr, *cx = nullptr, *cy = nullptr, *cz = nullptr;
+    double *ex = nullptr, *ey = nullptr, *ez = nullptr, *ss = nullptr, *ww = nullptr;
+    int32_t *SS = nullptr, *so = nullptr;
+    int *status = nullptr;
+    hipError_t e = hipSuccess;
+#define ALLOC(ptr, bytes) if (e == hipSuccess) e = hipMalloc(&(ptr), (bytes))
+    ALLOC(nx, d * N); ALLOC(ny, d * N); ALLOC(nz, d * N);
+    ALLOC(cx, d * count); ALLOC(cy, d * count); ALLOC(cz, d * count);
+    ALLOC(ex, d * count); ALLOC(ey, d * count); ALLOC(ez, d * count);
+    ALLOC(ss, d * count); ALLOC(ww, d * count * n);
+    ALLOC(SS, sizeof(int32_t) * count * n); ALLOC(so, sizeof(int32_t) * count);
+    ALLOC(status, sizeof(int) * ST_WORDS);
+#undef ALLOC
+    if (e == hipSuccess) e = upload_points(nodes_xyz, N, on_device, nx, ny, nz, s);
+    if (e == hipSuccess) e = upload_points(centers, count, on_device, cx, cy, cz, s);
+    if (e == hipSuccess) e = upload_points(evals, count, on_device, ex, ey, ez, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(ss, s2, d * count, in, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(SS, idx, sizeof(int32_t) * count * n, in, s);
+    if (e == hipSuccess) e = launch_status_reset(status, s);
+    if (e == hipSuccess) {
+        SolveArgs a{};
+        a.nx = nx; a.ny = ny; a.nz = nz; a.N = N;
+        a.ex = ex; a.ey = ey; a.ez = ez;
+        a.cx = cx; a.cy = cy; a.cz = cz;
+        a.S = SS; a.s2 = ss; a.cidx = nullptr;
+        a.count = count; a.n = n; a.L = Lr; a.k = kr;
+        a.w = ww; a.st_out = so; a.status = status; a.step = 0;
+        e = launch_solve(a, s);
+    }
+    const hipMemcpyKind out = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (e == hipSuccess) e = hipMemcpyAsync(w, ww, d * count * n, out, s);
+    if (e == hipSuccess && status_out) e = hipMemcpyAsync(status_out, so, sizeof(int32_t) * count, out, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    int code = RBFSL_OK;
+    if (e != hipSuccess) code = (e == hipErrorOutOfMemory) ? RBFSL_E_NOMEM : RBFSL_E_DEVICE;
+    void *bufs[] = {nx, ny, nz, cx, cy, cz, ex, ey, ez, ss, ww, SS, so, status};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    return code;
+}
+
+}  // extern "C"

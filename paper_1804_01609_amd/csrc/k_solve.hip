@@ -1,0 +1,48 @@
+// Dispatch of the stencil solver over its compiled capacities (the kernel
+// itself is in k_solve.h; each capacity is compiled in its own unit).
+#include "rbfsl_impl.h"
+
+namespace rbfsl {
+
+hipError_t solve_m47(const SolveArgs &a, hipStream_t s);
+hipError_t solve_m64(const SolveArgs &a, hipStream_t s);
+hipError_t solve_m81(const SolveArgs &a, hipStream_t s);
+hipError_t solve_m96(const SolveArgs &a, hipStream_t s);
+hipError_t solve_m121(const SolveArgs &a, hipStream_t s);
+hipError_t solve_m128(const SolveArgs &a, hipStream_t s);
+hipError_t solve_m185(const SolveArgs &a, hipStream_t s);
+
+struct Variant {
+    int mcap;
+    hipError_t (*fn)(const SolveArgs &, hipStream_t);
+};
+
+static const Variant kVariants[] = {
+    {47, solve_m47},
+    {64, solve_m64},
+    {81, solve_m81},
+    {96, solve_m96},
+    {121, solve_m121},
+    {128, solve_m128},
+    {185, solve_m185},
+};
+
+static const Variant *pick(int M) {
+    for (const Variant &v : kVariants)
+        if (M <= v.mcap) return &v;
+    return nullptr;
+}
+
+int solve_variant_capacity(int M) {
+    const Variant *v = pick(M);
+    return v ? v->mcap : 0;
+}
+
+hipError_t launch_solve(const SolveArgs &a, hipStream_t s) {
+    if (a.count <= 0) return hipSuccess;
+    const Variant *v = pick(a.n + (a.L + 1) * (a.L + 1));
+    if (!v) return hipErrorInvalidValue;
+    return v->fn(a, s);
+}
+
+}  // namespace rbfsl
