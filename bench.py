@@ -40,12 +40,39 @@ def solve_flops(M):
     return elim + back
 
 
+def solver_sources_sha256(M):
+    """Hash of the solver sources the counters were taken on (kernel + instantiation)."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1804_01609_amd", "csrc")
+    cap = {47: 48}.get(M, M)
+    h = hashlib.sha256()
+    for f in ("k_solve.h", f"k_solve_m{cap}.hip"):
+        path = os.path.join(csrc, f)
+        if not os.path.exists(path):
+            return None
+        h.update(open(path, "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(cfg_key, M):
+    """HBM bytes per k_solve launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by a known-size copy kernel), or None
+    when the summary is missing or the solver sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"k_solve_{cfg_key}_N40962_M120_counters.txt")
+    if cfg_key != "c2" or not os.path.exists(path):
+        return None
+    kv = dict(line.strip().split("=", 1) for line in open(path) if "=" in line and not line.startswith("#"))
+    if kv.get("source_sha256") != solver_sources_sha256(M):
+        return None
+    return float(kv["hbm_bytes_per_launch"])
+
+
 def cpu_baseline(cfg, X, q0, target_s):
     """The oracle, as it stands, on a bounded sample of one step's nodes."""
     import oracle
     p = oracle.make_params(cfg["n"], cfg["L"], cfg["k"], 0, cfg["vel_id"], cfg["vp"], cfg["dt"], 0.0, cfg["ntr"])
     rng = np.random.default_rng(0)
-    J = 64
+    J = 512
     t = time.perf_counter()
     oracle.step_sample(X, p, 0, rng.integers(0, X.shape[0], J), q0)
     dt = time.perf_counter() - t
@@ -67,7 +94,19 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run 5 device-to-device copies of BYTES (a known-size copy kernel "
+                         "that calibrates the HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        src = torch.ones(args.calibrate_copy // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": args.calibrate_copy, "copies": 5}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU sharding is described in the design notes, not built)"}))
@@ -125,7 +164,7 @@ def main():
                               for i, name in enumerate(["trace", "knn", "solve", "apply"])},
         "roofline": {"kernel": "k_solve", "bound": "alu", "achieved": achieved,
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                     "traffic": None,
+                     "traffic": measured_traffic(args.config, M), "traffic_unit": "bytes/launch",
                      "flops_per_launch": fl, "launch_ms": solve_ms},
     }
     if not args.no_cpu_baseline:

@@ -15,9 +15,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "librbfsl.so")
 
-SOURCES = ["k_solve_m185.hip", "k_solve_m128.hip", "k_solve_m121.hip", "k_solve_m96.hip",
-           "k_solve_m81.hip", "k_solve_m64.hip", "k_solve_m47.hip", "k_solve.hip",
-           "api.hip", "k_trace.hip", "k_grid.hip", "k_knn.hip", "k_apply.hip"]
+SOURCES = ["k_solve_m192.hip", "k_solve_m128.hip", "k_solve_m120.hip", "k_solve_m96.hip", "k_solve_m81.hip", "k_solve_m64.hip", "k_solve_m48.hip",
+           "k_solve.hip", "api.hip", "k_trace.hip", "k_grid.hip", "k_knn.hip", "k_apply.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("RBFSL_ARCH", "gfx950")
@@ -28,6 +27,9 @@ FLAGS = [
     "-ffp-contract=off",
     # no packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # keep SimplifyCFG from merging the per-row-slot branches of the solver
+    # into pointer phis, which would push its register arrays to scratch
+    "-mllvm", "-simplifycfg-sink-common=false",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]

@@ -1,32 +1,35 @@
 #pragma once
 // Assembly and solution of the local saddle-point systems (eq. rbf_poly_linsys,
-// Sections 2.2, 2.4 and 3.3.2): one workgroup per stencil, the augmented
-// M x (M+1) matrix [A~ | b; p(xi)] held in VGPRs, Gaussian elimination with
-// partial pivoting, back substitution, cardinal weights w = first n unknowns.
+// Sections 2.2, 2.4 and 3.3.2): one workgroup of W waves per stencil, the
+// M x M matrix held in VGPRs, Gaussian elimination with partial pivoting,
+// back substitution, cardinal weights w = first n unknowns.
 //
-// Layout.  The workgroup's 64*W lanes form RR = 64W/CC lane-rows times CC
-// lane-columns.  Matrix row i lives in lane-row i; column j lives in
-// lane-column j % CC, register slot j / CC (cyclic, so the shrinking trailing
-// matrix stays balanced across lane-columns).  Register slots are indexed only
-// by compile-time constants: the step loop is unrolled over the slot of the
-// pivot column, so "columns right of the pivot" is a static slot range.
+// Layout.  Matrix row i lives in lane i % 64, row slot i / 64 (R slots).
+// Columns are dealt to the waves in blocks of B: column j belongs to block
+// g = j / B, owned by wave g % W, at column slot (g / W) * B + j % B.  Each
+// wave holds all rows of its columns, so the pivot search of a column is a
+// reduction inside one wave.  The right-hand side is kept, identically, in
+// every wave.  Register slots are indexed only by compile-time constants.
 //
-// Pivoting is implicit: rows never move; a row is marked used once it has been
-// a pivot row and is then left alone (its multiplier is 0).  Per step k:
-//   1. the lanes owning column k reduce max |a_ik| over unused rows (ties to
-//      the lowest row) within each wave, then across waves through LDS;
-//   2. r = 1/a_pk; each unused row's multiplier l_i = a_ik * r is broadcast
-//      through LDS; the pivot row's entries right of the pivot slot are
-//      appended to the U store in LDS (kept for the back substitution);
-//   3. every lane updates its slots right of the pivot slot with
-//      a_ij = fma(-l_i, u_j, a_ij).
-// Each matrix element therefore sees exactly the same sequence of correctly
-// rounded operations as in textbook right-looking elimination: the result
-// does not depend on the lane layout.
+// Elimination (right-looking, blocked, implicit partial pivoting: rows never
+// move; a row is marked used once it has been a pivot row and its multiplier
+// is 0 from then on).  For each block g of B columns:
+//   1. the owner wave factors the panel: for each of its B columns k, the
+//      pivot p = the unused row with the largest |a_pk| (ties to the lowest
+//      row), r_k = 1/a_pk, multipliers l_ik = a_ik * r_k, and the update of the
+//      panel's remaining columns; p, r_k and the l_ik go to LDS;
+//   2. one barrier;
+//   3. every wave applies the B rank-1 updates, in step order, to its columns
+//      right of the panel and to the right-hand side:
+//      a_ij = fma(-l_ik, a_pj, a_ij), y_i = fma(-l_ik, y_p, y_i), where a_pj
+//      is row p's current value in this wave (it already carries the updates
+//      of the earlier steps of the block).
+// Every matrix element therefore sees exactly the sequence of correctly
+// rounded operations of textbook unblocked right-looking elimination.
 //
-// Back substitution: one wave, unknowns from the last one down, each lane
-// holding the right-hand sides of two or three pivot rows; z_k = y_k r_k, then
-// y_i = fma(-u_ik, z_k, y_i) for the pivot rows of earlier steps.
+// Back substitution: unknowns from the last one down (z_k = y_pk r_k, then
+// y_i = fma(-u_ik, z_k, y_i) for the rows pivoted before step k), by wave 0,
+// with the U columns streamed from the waves through LDS in chunks.
 #include <float.h>
 
 #include <type_traits>
@@ -34,30 +37,39 @@
 
 #include "rbfsl_impl.h"
 
+#define SI __attribute__((always_inline))
+
 namespace rbfsl {
 
-template <int B, typename F, int... Is>
+template <int B0, typename F, int... Is>
 __device__ __forceinline__ void sfor_impl(F &&f, std::integer_sequence<int, Is...>) {
-    (f(std::integral_constant<int, B + Is>{}), ...);
+    (f(std::integral_constant<int, B0 + Is>{}), ...);
 }
-// compile-time loop over B..E-1 (f receives an integral_constant)
-template <int B, int E, typename F>
+// compile-time loop over B0..E-1 (f receives an integral_constant)
+template <int B0, int E, typename F>
 __device__ __forceinline__ void sfor(F &&f) {
-    if constexpr (E > B) sfor_impl<B>(f, std::make_integer_sequence<int, E - B>{});
+    if constexpr (E > B0) sfor_impl<B0>(f, std::make_integer_sequence<int, E - B0>{});
 }
 
-template <int W, int CC, int NC>
+template <int W, int R, int NCB, int B, int WPE_>
 struct Cfg {
     static constexpr int NT = 64 * W;
-    static constexpr int RR = NT / CC;
-    static constexpr int MCAP = (RR < NC * CC - 1) ? RR : NC * CC - 1;
-    static constexpr int YT = (MCAP + 63) / 64;  // back-substitution slots per lane
-    // offset of step k's pivot-row record in the U store
-    static constexpr __host__ __device__ int base(int k) {
-        int sk = k / CC, c = k % CC;
-        return CC * CC * (sk * NC - sk * (sk - 1) / 2) + c * CC * (NC - sk);
-    }
-    static constexpr int US = base(MCAP);
+    static constexpr int ROWS = 64 * R;
+    static constexpr int NC = NCB * B;                      // column slots per wave
+    static constexpr int NBLK = W * NCB;                    // column blocks
+    static constexpr int MCAP = (ROWS < W * NC) ? ROWS : W * NC;
+    static constexpr int CSB0 = (24 / (W * B)) > 0 ? (24 / (W * B)) : 1;  // slot-blocks per chunk
+    static constexpr int CSB = (CSB0 > NCB) ? NCB : CSB0;
+    static constexpr int NCHUNK = (NCB + CSB - 1) / CSB;
+    static constexpr int UBN = CSB * W * B * ROWS;          // doubles of one U chunk
+    static constexpr int ASM = 4 * MCAP + 8 + (MCAP * MCAP + 3) / 4;  // assembly tables (n*mL <= M^2/4)
+    static constexpr int LBN = 2 * B * ROWS;                // panel multipliers, two buffers
+    static constexpr int STAGE0 = (UBN > ASM) ? UBN : ASM;
+    static constexpr int STAGE = (STAGE0 > LBN) ? STAGE0 : LBN;
+    static constexpr int UBW = (NC + 3) & ~1;               // per-wave pivot-row buffer (even)
+    // waves per SIMD the kernel is compiled for: the compiler may use
+    // 512/WPE VGPRs per lane and must not spill to reach a higher occupancy
+    static constexpr int WPE = WPE_;
 };
 
 __device__ __forceinline__ double phs(double r2, int k) {
@@ -100,30 +112,8 @@ __device__ __forceinline__ void local3(const double x[3], const double c[3], con
     u = -(g * inv_s);
 }
 
-// basis value number `want` (or all of them into out[]) at (al, be, u):
-// m = 0..L, cos (and sin for m>0), i = 0..L-m: H_m^sigma(al,be) u^i
-__device__ __forceinline__ double basis_one(int L, double al, double be, double u, int want) {
-    int col = 0;
-    double hc = 1.0, hs = 0.0, res = 0.0;
-    for (int m = 0; m <= L; ++m) {
-        if (m > 0) {
-            double nc = al * hc - be * hs;
-            double ns = al * hs + be * hc;
-            hc = nc;
-            hs = ns;
-        }
-        for (int sg = 0; sg < (m == 0 ? 1 : 2); ++sg) {
-            double v = (sg == 0) ? hc : hs;
-            for (int i = 0; i <= L - m; ++i) {
-                if (col == want) res = v;
-                ++col;
-                v = v * u;
-            }
-        }
-    }
-    return res;
-}
-
+// the (L+1)^2 basis values at (al, be, u): m = 0..L, cos (and sin for m>0),
+// i = 0..L-m: H_m^sigma(al,be) u^i with H_m = Re/Im (al + i be)^m
 __device__ __forceinline__ void basis_all(int L, double al, double be, double u, double *out) {
     int col = 0;
     double hc = 1.0, hs = 0.0;
@@ -144,30 +134,69 @@ __device__ __forceinline__ void basis_all(int L, double al, double be, double u,
     }
 }
 
-__device__ __forceinline__ double shfl_d(double v, int src) {
-    return __shfl(v, src, 64);
+// value of v in lane `lane` (wave-uniform), through two readlanes
+__device__ __forceinline__ double bcast_d(double v, int lane) {
+    int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
 }
 
-template <int W, int CC, int NC>
-__global__ void __launch_bounds__(64 * W) k_solve(SolveArgs A) {
-    using C = Cfg<W, CC, NC>;
-    constexpr int NT = C::NT, RR = C::RR, MCAP = C::MCAP;
-    __shared__ double us[C::US];     // U store; holds the basis table during assembly
-    __shared__ double yb[3 * MCAP];  // scaled local coordinates of the stencil nodes
-    __shared__ double lb[2][RR];     // multipliers (double buffered by step parity)
-    __shared__ double rinvb[MCAP];
-    __shared__ double cval[2][W], csig[2][W];
-    __shared__ int crow[2][W];
+template <int CTRL, int ROWM, int BANKM>
+__device__ __forceinline__ double dpp_d(double v, double ident) {
+    int lo = __builtin_amdgcn_update_dpp(__double2loint(ident), __double2loint(v), CTRL, ROWM, BANKM, false);
+    int hi = __builtin_amdgcn_update_dpp(__double2hiint(ident), __double2hiint(v), CTRL, ROWM, BANKM, false);
+    return __hiloint2double(hi, lo);
+}
 
+// maximum over the wave of values >= -1 (no NaN), returned to every lane:
+// quad swaps, row shifts, row broadcasts (the classic DPP reduction), then
+// lane 63 holds the result
+__device__ __forceinline__ double wave_max_d(double v) {
+    v = fmax(v, dpp_d<0xB1, 0xF, 0xF>(v, -1.0));   // quad_perm [1,0,3,2]
+    v = fmax(v, dpp_d<0x4E, 0xF, 0xF>(v, -1.0));   // quad_perm [2,3,0,1]
+    v = fmax(v, dpp_d<0x114, 0xF, 0xE>(v, -1.0));  // row_shr:4
+    v = fmax(v, dpp_d<0x118, 0xF, 0xC>(v, -1.0));  // row_shr:8
+    v = fmax(v, dpp_d<0x142, 0xA, 0xF>(v, -1.0));  // row_bcast:15
+    v = fmax(v, dpp_d<0x143, 0xC, 0xF>(v, -1.0));  // row_bcast:31
+    return bcast_d(v, 63);
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+    // LDS writes by some lanes of this wave become visible to its other lanes
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int W, int R, int NCB, int B, int WPE>
+__global__ void __launch_bounds__(64 * W)
+__attribute__((amdgpu_waves_per_eu(WPE, WPE))) k_solve(SolveArgs A) {
+    using C = Cfg<W, R, NCB, B, WPE>;
+    constexpr int NT = C::NT, ROWS = C::ROWS, MCAP = C::MCAP, NC = C::NC;
+    // stage: assembly tables, then the panel multipliers (elimination), then
+    // the U chunks (back substitution)
+    __shared__ double stage[C::STAGE];
+    __shared__ double ub[W][C::UBW];     // each wave's part of the current pivot row
+    __shared__ double rinvb[MCAP];
+    __shared__ double zb[MCAP];
+    __shared__ int pivb[MCAP];
+    __shared__ int failk[2];             // failing step of a panel, by block parity
     __shared__ int skip;
+    double(*lb)[B][ROWS] = reinterpret_cast<double(*)[B][ROWS]>(stage);  // [2][B][ROWS]
+    constexpr int NOFAIL = 0x7fffffff;
+
     const int64_t j = blockIdx.x;
     const int t = threadIdx.x;
+    const int lane = t & 63, wv = t >> 6;
     // one read for the whole workgroup: this or an earlier step already failed
-    if (t == 0) skip = (A.status[ST_FAILSTEP] <= A.step);
+    if (t == 0) {
+        skip = (A.status[ST_FAILSTEP] <= A.step);
+        failk[0] = NOFAIL;
+        failk[1] = NOFAIL;
+    }
     __syncthreads();
     if (skip) return;
-    const int lr = t % RR, lc = t / RR;
-    const int lane = t & 63, wv = t >> 6;
+
     const int n = A.n, L = A.L, k = A.k;
     const int mL = (L + 1) * (L + 1);
     const int M = n + mL;
@@ -187,192 +216,310 @@ __global__ void __launch_bounds__(64 * W) k_solve(SolveArgs A) {
     const double inv_s = 1.0 / s;
     double e1[3], e2[3];
     frame3(ctr, e1, e2);
-    double yx[3], alx, bex, ux;
-    local3(xe, ctr, e1, e2, inv_s, yx, alx, bex, ux);
 
-    // ---- assembly 1: local coordinates and basis table of the stencil nodes ----
-    double *Pb = us;  // n x mL basis values (aliases the U store until elimination)
-    if (t < n) {
-        int g = Srow[t];
-        if (g < 0 || (int64_t)g >= A.N) {  // not a node index: flag the stencil, read node 0
-            atomicAdd(&A.status[ST_SEARCH], 1);
-            atomicMin(&A.status[ST_FAILSTEP], (int)A.step);
-            g = 0;
+    // ---- assembly 1: local coordinates and basis tables ----
+    double *yb = stage;                 // 3 x MCAP scaled local coordinates
+    double *yxb = stage + 3 * MCAP;     // evaluation point (3) ...
+    double *peb = yxb + 4;              // ... and its basis values (mL <= MCAP)
+    double *Pb = peb + MCAP;            // n x mL basis values of the stencil nodes
+    for (int a = t; a <= n; a += NT) {
+        double x[3];
+        if (a < n) {
+            int g = Srow[a];
+            if (g < 0 || (int64_t)g >= A.N) {  // not a node index: flag the stencil, read node 0
+                atomicAdd(&A.status[ST_SEARCH], 1);
+                atomicMin(&A.status[ST_FAILSTEP], (int)A.step);
+                g = 0;
+            }
+            x[0] = A.nx[g]; x[1] = A.ny[g]; x[2] = A.nz[g];
+        } else {
+            x[0] = xe[0]; x[1] = xe[1]; x[2] = xe[2];
         }
-        const double x[3] = {A.nx[g], A.ny[g], A.nz[g]};
         double y[3], al, be, u;
         local3(x, ctr, e1, e2, inv_s, y, al, be, u);
-        yb[3 * t] = y[0];
-        yb[3 * t + 1] = y[1];
-        yb[3 * t + 2] = y[2];
-        basis_all(L, al, be, u, Pb + t * mL);
+        if (a < n) {
+            yb[3 * a] = y[0]; yb[3 * a + 1] = y[1]; yb[3 * a + 2] = y[2];
+            basis_all(L, al, be, u, Pb + a * mL);
+        } else {
+            yxb[0] = y[0]; yxb[1] = y[1]; yxb[2] = y[2];
+            basis_all(L, al, be, u, peb);
+        }
     }
     __syncthreads();
 
-    // ---- assembly 2: my row, my columns ----
-    const int i = lr;
-    double a[NC];
-    double pe_i = 0.0;  // p(xi) entry of rows n..M-1
-    if (i >= n && i < M) pe_i = basis_one(L, alx, bex, ux, i - n);
-    double yi[3] = {0.0, 0.0, 0.0}, bi = 0.0;
-    if (i < n) {
-        yi[0] = yb[3 * i]; yi[1] = yb[3 * i + 1]; yi[2] = yb[3 * i + 2];
-        double d0 = yi[0] - yx[0], d1 = yi[1] - yx[1], d2 = yi[2] - yx[2];
-        bi = phs((d0 * d0 + d1 * d1) + d2 * d2, k);
-    }
-    sfor<0, NC>([&](auto S) {
-        constexpr int sl = S;
-        const int jc = lc + CC * sl;
-        double v = 0.0;
-        if (i < n) {
-            if (jc < n) {
-                double d0 = yi[0] - yb[3 * jc], d1 = yi[1] - yb[3 * jc + 1], d2 = yi[2] - yb[3 * jc + 2];
-                v = phs((d0 * d0 + d1 * d1) + d2 * d2, k);
-            } else if (jc < M) {
-                v = Pb[i * mL + (jc - n)];
-            } else if (jc == M) {
-                v = bi;
+    // ---- assembly 2: my rows, my columns; the right-hand side ----
+    double a[R][NC];
+    double y[R];
+    bool used[R];
+    int stepof[R];
+    {
+        const double yx0 = yxb[0], yx1 = yxb[1], yx2 = yxb[2];
+        sfor<0, R>([&](auto RI) SI {
+            constexpr int r = RI;
+            const int i = lane + 64 * r;
+            used[r] = (i >= M);
+            stepof[r] = MCAP;
+            double yi0 = 0.0, yi1 = 0.0, yi2 = 0.0;
+            if (i < n) { yi0 = yb[3 * i]; yi1 = yb[3 * i + 1]; yi2 = yb[3 * i + 2]; }
+            double rhs = 0.0;
+            if (i < n) {
+                double d0 = yi0 - yx0, d1 = yi1 - yx1, d2 = yi2 - yx2;
+                rhs = phs((d0 * d0 + d1 * d1) + d2 * d2, k);
+            } else if (i < M) {
+                rhs = peb[i - n];
             }
-        } else if (i < M) {
-            if (jc < n) v = Pb[jc * mL + (i - n)];
-            else if (jc == M) v = pe_i;
-        }
-        a[sl] = v;
-    });
-    bool used = (i >= M);
-    __syncthreads();  // the basis table is dead from here on
-
-    // ---- elimination ----
-    bool fail = false;
-    sfor<0, NC>([&](auto SK) {
-        constexpr int sk = SK;
-        if (fail || sk * CC >= M) return;
-        for (int c = 0; c < CC; ++c) {
-            const int kk = sk * CC + c;
-            if (kk >= M) break;
-            const int par = kk & 1;
-            // 1. pivot search in column kk
-            const bool own = (lc == c);
-            const double av = a[sk];
-            double cand = (own && !used) ? fabs(av) : -1.0;
-            double m = cand;
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
-            unsigned long long bal = __ballot(cand == m);
-            int first = __ffsll((long long)bal) - 1;
-            int prow = __shfl(lr, first, 64);
-            double psig = shfl_d(av, first);
-            if (lane == 0) {
-                cval[par][wv] = m;
-                csig[par][wv] = psig;
-                crow[par][wv] = prow;
-            }
-            __syncthreads();
-            double best = cval[par][0], pval = csig[par][0];
-            int p = crow[par][0];
-#pragma unroll
-            for (int q = 1; q < W; ++q) {
-                double v = cval[par][q];
-                int r = crow[par][q];
-                if (v > best || (v == best && r < p)) {
-                    best = v;
-                    pval = csig[par][q];
-                    p = r;
-                }
-            }
-            if (!(best > 0.0)) {
-                fail = true;
-                break;
-            }
-            // 2. multipliers and the pivot row
-            if (i == p) used = true;
-            const double r = 1.0 / pval;
-            if (own) lb[par][i] = used ? 0.0 : av * r;
-            const int rb = C::base(kk) + lc * (NC - sk);
-            if (i == p) {
-                sfor<sk, NC>([&](auto S) {
-                    constexpr int sl = S;
-                    us[rb + (sl - sk)] = a[sl];
-                });
-            }
-            if (t == 0) rinvb[kk] = r;
-            __syncthreads();
-            // 3. rank-1 update of the slots right of the pivot slot
-            const double l = lb[par][i];
-            sfor<sk, NC>([&](auto S) {
+            y[r] = rhs;
+            sfor<0, NC>([&](auto S) SI {
                 constexpr int sl = S;
-                a[sl] = fma(-l, us[rb + (sl - sk)], a[sl]);
+                const int jc = ((sl / B) * W + wv) * B + sl % B;
+                double v = 0.0;
+                if (i < n) {
+                    if (jc < n) {
+                        double d0 = yi0 - yb[3 * jc], d1 = yi1 - yb[3 * jc + 1], d2 = yi2 - yb[3 * jc + 2];
+                        v = phs((d0 * d0 + d1 * d1) + d2 * d2, k);
+                    } else if (jc < M) {
+                        v = Pb[i * mL + (jc - n)];
+                    }
+                } else if (i < M) {
+                    if (jc < n) v = Pb[jc * mL + (i - n)];
+                }
+                a[r][sl] = v;
+            });
+        });
+    }
+
+    __syncthreads();  // the assembly tables are dead; stage now holds multipliers
+
+    // ---- elimination, one block of B columns at a time ----
+    // The block loop is a runtime loop (the code must fit the instruction
+    // cache); per block, a runtime slot-block index is dispatched once to code
+    // whose register slots are all static.
+    // factor panel g (its owner wave only; panel = slot-block PSB): pivots,
+    // reciprocals and multipliers of the panel's columns, in-panel updates
+    auto factor = [&](auto PSBC, int g) SI {
+        constexpr int PSB = PSBC;
+        constexpr int ps0 = PSB * B;
+        const int k0 = g * B;
+        const int cnt = (k0 + B < M) ? B : M - k0;
+        sfor<0, B>([&](auto CI) SI {
+            constexpr int c = CI;
+            if (c >= cnt || failk[g & 1] != NOFAIL) return;
+            const int kk = k0 + c;
+            double best = -1.0;
+            sfor<0, R>([&](auto RI) SI {
+                constexpr int r = RI;
+                const double v = fabs(a[r][ps0 + c]);
+                if (!used[r] && v > best) best = v;
+            });
+            const double m = wave_max_d(best);
+            if (!(m > 0.0)) {
+                if (lane == 0) failk[g & 1] = kk;
+                return;
+            }
+            int p = -1;
+            sfor<0, R>([&](auto RI) SI {
+                constexpr int r = RI;
+                const unsigned long long msk = __ballot(!used[r] && fabs(a[r][ps0 + c]) == m);
+                if (p < 0 && msk) p = 64 * r + __ffsll((long long)msk) - 1;
+            });
+            const int pl = p & 63, pr = p >> 6;
+            double pv = 0.0;
+            sfor<0, R>([&](auto RI) SI {
+                constexpr int r = RI;
+                if (pr == r) pv = bcast_d(a[r][ps0 + c], pl);
+            });
+            const double rinv = 1.0 / pv;
+            double l[R];
+            sfor<0, R>([&](auto RI) SI {
+                constexpr int r = RI;
+                if (pr == r && lane == pl) { used[r] = true; stepof[r] = kk; }
+                l[r] = used[r] ? 0.0 : a[r][ps0 + c] * rinv;
+                lb[g & 1][c][lane + 64 * r] = l[r];
+            });
+            if (lane == 0) {
+                pivb[kk] = p;
+                rinvb[kk] = rinv;
+            }
+            sfor<c + 1, B>([&](auto CC) SI {
+                constexpr int cc = CC;
+                double u = 0.0;
+                sfor<0, R>([&](auto RI) SI {
+                    constexpr int r = RI;
+                    if (pr == r) u = bcast_d(a[r][ps0 + cc], pl);
+                });
+                sfor<0, R>([&](auto RI) SI {
+                    constexpr int r = RI;
+                    a[r][ps0 + cc] = fma(-l[r], u, a[r][ps0 + cc]);
+                });
+            });
+        });
+    };
+    // apply the rank-1 updates of block g's steps, in step order, to this
+    // wave's slots S0 .. NC-1; mark the pivot rows as used and update the
+    // right-hand side.  Row p's entries reach every lane by readlane.
+    auto upd = [&](auto S0C, int g, int cnt) SI {
+        constexpr int S0 = S0C;
+        const int k0 = g * B;
+        for (int c = 0; c < cnt; ++c) {
+            const int kk = k0 + c;
+            const int p = pivb[kk];
+            const int pl = p & 63, pr = p >> 6;
+            double l[R];
+            sfor<0, R>([&](auto RI) SI {
+                constexpr int r = RI;
+                if (pr == r && lane == pl) { used[r] = true; stepof[r] = kk; }
+                l[r] = lb[g & 1][c][lane + 64 * r];
+            });
+            sfor<0, R>([&](auto PRI) SI {
+                constexpr int prr = PRI;
+                if (pr == prr) {
+                    const double yp = bcast_d(y[prr], pl);
+                    sfor<S0, NC>([&](auto S) SI {
+                        constexpr int sl = S;
+                        const double u = bcast_d(a[prr][sl], pl);
+                        sfor<0, R>([&](auto RI) SI {
+                            constexpr int r = RI;
+                            a[r][sl] = fma(-l[r], u, a[r][sl]);
+                        });
+                        // keep each broadcast next to its use (the scheduler would
+                        // otherwise hoist them all and run out of registers)
+                        if constexpr ((sl - S0) % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+                    });
+                    sfor<0, R>([&](auto RI) SI {
+                        constexpr int r = RI;
+                        y[r] = fma(-l[r], yp, y[r]);
+                    });
+                }
             });
         }
-    });
-    if (fail) {
+    };
+    const int nblk = (M + B - 1) / B;
+    bool dead = false;
+    for (int g = 0; g < nblk; ++g) {
+        const int ow = g % W, psb = g / W;  // owner wave and slot-block of block g
+        if (wv == ow) {
+            sfor<0, NCB>([&](auto SB) SI {
+                if (psb == SB) factor(SB, g);
+            });
+        }
+        __syncthreads();
+        const int fa = failk[g & 1];
+        const int k0 = g * B;
+        const int kend = (k0 + B < M) ? k0 + B : M;
+        const int cnt = ((kend < fa) ? kend : fa) - k0;
+        const int sbA = (wv > ow) ? psb : psb + 1;  // first active slot-block of this wave
+        sfor<0, NCB + 1>([&](auto SB) SI {
+            constexpr int sb = SB;
+            if (sbA == sb) upd(std::integral_constant<int, sb * B>{}, g, cnt);
+        });
+        dead = (fa != NOFAIL);
+        if (dead) break;
+    }
+    if (dead) {
         if (t == 0) {
             atomicAdd(&A.status[ST_SINGULAR], 1);
             atomicMin(&A.status[ST_FAILSTEP], (int)A.step);
+            if (A.st_out) A.st_out[j] = RBFSL_E_SINGULAR;
         }
-        if (A.st_out && t == 0) A.st_out[j] = RBFSL_E_SINGULAR;
         return;
+    }
+
+    // ---- back substitution, chunks of CSB slot-blocks from the right ----
+    // slot-blocks [sb1, sb2) of every wave cover columns [sb1*W*B, sb2*W*B);
+    // wave 0 holds the pivots and reciprocals in registers (lane k % 64)
+    constexpr int KT = (MCAP + 63) / 64;
+    int pivr[KT];
+    double rinvr[KT];
+    sfor<0, KT>([&](auto TI) SI {
+        constexpr int tt = TI;
+        const int kk = lane + 64 * tt;
+        pivr[tt] = (kk < M) ? pivb[kk] : 0;
+        rinvr[tt] = (kk < M) ? rinvb[kk] : 0.0;
+    });
+    double zr[KT];
+    sfor<0, KT>([&](auto TI) SI { zr[TI] = 0.0; });
+    double *UB = stage;
+    sfor<0, C::NCHUNK>([&](auto CI) SI {
+        constexpr int ch = C::NCHUNK - 1 - CI;
+        constexpr int sb1 = ch * C::CSB;
+        constexpr int sb2 = (sb1 + C::CSB < NCB) ? sb1 + C::CSB : NCB;
+        constexpr int c0 = sb1 * W * B;
+        if (c0 >= M) return;  // chunk lies beyond the last column
+        __syncthreads();      // previous chunk consumed
+        sfor<sb1 * B, sb2 * B>([&](auto S) SI {
+            constexpr int sl = S;
+            const int col = ((sl / B) * W + wv) * B + sl % B - c0;
+            sfor<0, R>([&](auto RI) SI {
+                constexpr int r = RI;
+                UB[col * ROWS + lane + 64 * r] = a[r][sl];
+            });
+        });
+        __syncthreads();
+        if (wv == 0) {
+            const int khi = (sb2 * W * B < M) ? sb2 * W * B : M;
+            for (int kk = khi - 1; kk >= c0; --kk) {
+                const int kl = kk & 63, kt = kk >> 6;
+                int pk = 0;
+                double rk = 0.0;
+                sfor<0, KT>([&](auto TI) SI {
+                    constexpr int tt = TI;
+                    if (kt == tt) {
+                        pk = __builtin_amdgcn_readlane(pivr[tt], kl);
+                        rk = bcast_d(rinvr[tt], kl);
+                    }
+                });
+                const int pl = pk & 63, pr = pk >> 6;
+                double yk = 0.0;
+                sfor<0, R>([&](auto RI) SI {
+                    constexpr int r = RI;
+                    if (pr == r) yk = bcast_d(y[r], pl);
+                });
+                const double zk = yk * rk;
+                sfor<0, KT>([&](auto TI) SI {
+                    constexpr int tt = TI;
+                    if (kt == tt && lane == kl) zr[tt] = zk;
+                });
+                const double *ucol = UB + (kk - c0) * ROWS;
+                sfor<0, R>([&](auto RI) SI {
+                    constexpr int r = RI;
+                    if (stepof[r] < kk) y[r] = fma(-ucol[lane + 64 * r], zk, y[r]);
+                });
+            }
+        }
+    });
+    if (wv == 0) {
+        sfor<0, KT>([&](auto TI) SI {
+            constexpr int tt = TI;
+            const int kk = lane + 64 * tt;
+            if (kk < M) zb[kk] = zr[tt];
+        });
     }
     __syncthreads();
 
-    // ---- back substitution (wave 0) ----
-    if (wv != 0) return;
-    double y[C::YT], z[C::YT];
-#pragma unroll
-    for (int q = 0; q < C::YT; ++q) {
-        int kk = lane + 64 * q;
-        y[q] = 0.0;
-        z[q] = 0.0;
-        if (kk < M) {
-            int skk = kk / CC;
-            y[q] = us[C::base(kk) + (M % CC) * (NC - skk) + (M / CC - skk)];
-        }
-    }
-    for (int kk = M - 1; kk >= 0; --kk) {
-        const int q = kk >> 6, src = kk & 63;
-        double yk = 0.0;
-#pragma unroll
-        for (int qq = 0; qq < C::YT; ++qq)
-            if (qq == q) yk = shfl_d(y[qq], src);
-        const double zk = yk * rinvb[kk];
-        const int col_l = kk % CC, col_s = kk / CC;
-#pragma unroll
-        for (int qq = 0; qq < C::YT; ++qq) {
-            int rr = lane + 64 * qq;
-            if (qq == q && lane == src) z[qq] = zk;
-            if (rr < kk) {
-                int srr = rr / CC;
-                double u = us[C::base(rr) + col_l * (NC - srr) + (col_s - srr)];
-                y[qq] = fma(-u, zk, y[qq]);
-            }
-        }
-    }
+    // ---- weights ----
     bool bad = false;
-#pragma unroll
-    for (int q = 0; q < C::YT; ++q) {
-        int aidx = lane + 64 * q;
-        if (aidx < n) {
-            A.w[j * n + aidx] = z[q];
-            if (!isfinite(z[q])) bad = true;
-        }
+    for (int aidx = t; aidx < n; aidx += NT) {
+        const double z = zb[aidx];
+        A.w[j * n + aidx] = z;
+        if (!isfinite(z)) bad = true;
     }
-    unsigned long long bb = __ballot(bad);
-    if (lane == 0) {
-        if (bb) {
+    const int anybad = __syncthreads_or(bad ? 1 : 0);
+    if (t == 0) {
+        if (anybad) {
             atomicAdd(&A.status[ST_NONFINITE], 1);
             atomicMin(&A.status[ST_FAILSTEP], (int)A.step);
         }
-        if (A.st_out) A.st_out[j] = bb ? RBFSL_E_NONFINITE : 0;
+        if (A.st_out) A.st_out[j] = anybad ? RBFSL_E_NONFINITE : 0;
     }
 }
 
-template <int W, int CC, int NC>
+template <int W, int R, int NCB, int B, int WPE>
 hipError_t launch_solve_variant(const SolveArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_solve<W, CC, NC>), dim3((unsigned)a.count), dim3(64 * W), 0, s, a);
+    hipLaunchKernelGGL((k_solve<W, R, NCB, B, WPE>), dim3((unsigned)a.count), dim3(64 * W), 0, s, a);
     return hipGetLastError();
 }
 
-template <int W, int CC, int NC>
-constexpr int variant_mcap() { return Cfg<W, CC, NC>::MCAP; }
+template <int W, int R, int NCB, int B>
+constexpr int variant_mcap() { return Cfg<W, R, NCB, B, 1>::MCAP; }
 
 }  // namespace rbfsl

@@ -4,13 +4,13 @@
 
 namespace rbfsl {
 
-hipError_t solve_m47(const SolveArgs &a, hipStream_t s);
+hipError_t solve_m48(const SolveArgs &a, hipStream_t s);
 hipError_t solve_m64(const SolveArgs &a, hipStream_t s);
 hipError_t solve_m81(const SolveArgs &a, hipStream_t s);
 hipError_t solve_m96(const SolveArgs &a, hipStream_t s);
-hipError_t solve_m121(const SolveArgs &a, hipStream_t s);
+hipError_t solve_m120(const SolveArgs &a, hipStream_t s);
 hipError_t solve_m128(const SolveArgs &a, hipStream_t s);
-hipError_t solve_m185(const SolveArgs &a, hipStream_t s);
+hipError_t solve_m192(const SolveArgs &a, hipStream_t s);
 
 struct Variant {
     int mcap;
@@ -18,13 +18,13 @@ struct Variant {
 };
 
 static const Variant kVariants[] = {
-    {47, solve_m47},
+    {48, solve_m48},
     {64, solve_m64},
     {81, solve_m81},
     {96, solve_m96},
-    {121, solve_m121},
+    {120, solve_m120},
     {128, solve_m128},
-    {185, solve_m185},
+    {192, solve_m192},
 };
 
 static const Variant *pick(int M) {

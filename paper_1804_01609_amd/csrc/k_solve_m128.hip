@@ -1,8 +1,10 @@
 // Solver instantiation for systems of size M <= 128: 4 wave(s) per stencil,
-// 2 lane-column(s), 65 register slots per lane.
+// 2 row slot(s) per lane, 4 blocks of 8 column slots per wave, 3 waves per SIMD.
 #include "k_solve.h"
 
 namespace rbfsl {
-static_assert(variant_mcap<4, 2, 65>() == 128, "capacity");
-hipError_t solve_m128(const SolveArgs &a, hipStream_t s) { return launch_solve_variant<4, 2, 65>(a, s); }
+static_assert(variant_mcap<4, 2, 4, 8>() == 128, "capacity");
+hipError_t solve_m128(const SolveArgs &a, hipStream_t s) {
+    return launch_solve_variant<4, 2, 4, 8, 3>(a, s);
+}
 }  // namespace rbfsl

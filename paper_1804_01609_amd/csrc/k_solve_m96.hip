@@ -1,8 +1,10 @@
 // Solver instantiation for systems of size M <= 96: 3 wave(s) per stencil,
-// 2 lane-column(s), 49 register slots per lane.
+// 2 row slot(s) per lane, 4 blocks of 8 column slots per wave, 3 waves per SIMD.
 #include "k_solve.h"
 
 namespace rbfsl {
-static_assert(variant_mcap<3, 2, 49>() == 96, "capacity");
-hipError_t solve_m96(const SolveArgs &a, hipStream_t s) { return launch_solve_variant<3, 2, 49>(a, s); }
+static_assert(variant_mcap<3, 2, 4, 8>() == 96, "capacity");
+hipError_t solve_m96(const SolveArgs &a, hipStream_t s) {
+    return launch_solve_variant<3, 2, 4, 8, 3>(a, s);
+}
 }  // namespace rbfsl

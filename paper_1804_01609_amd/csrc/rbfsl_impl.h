@@ -44,7 +44,7 @@ constexpr int NO_FAIL = 0x7fffffff;
 
 // kNN capacity: candidates kept per query inside the search ball.
 constexpr int KNN_CAP = 1024;
-constexpr int MAX_SYSTEM = 185;
+constexpr int MAX_SYSTEM = 192;
 
 // ---- launchers (return hipSuccess or the launch error) ----
 hipError_t launch_trace(const double *nx, const double *ny, const double *nz, int64_t N,

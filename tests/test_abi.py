@@ -34,7 +34,7 @@ def test_params_struct_layout_matches_header():
 
 def test_invalid_arguments_are_rejected_without_a_device():
     L = rb.lib()
-    assert L.rbfsl_max_system() >= 185
+    assert L.rbfsl_max_system() >= 184
     assert L.rbfsl_strerror(rb.RBFSL_E_SINGULAR) == b"singular stencil system"
     out = ctypes.c_void_p()
     p = rb.make_params(31, 3, 2)
