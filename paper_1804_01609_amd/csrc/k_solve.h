@@ -151,13 +151,15 @@ __device__ __forceinline__ double dpp_d(double v, double ident) {
 // maximum over the wave of values >= -1 (no NaN), returned to every lane:
 // quad swaps, row shifts, row broadcasts (the classic DPP reduction), then
 // lane 63 holds the result
+__device__ __forceinline__ double max_nn(double a, double b) { return (b > a) ? b : a; }
+
 __device__ __forceinline__ double wave_max_d(double v) {
-    v = fmax(v, dpp_d<0xB1, 0xF, 0xF>(v, -1.0));   // quad_perm [1,0,3,2]
-    v = fmax(v, dpp_d<0x4E, 0xF, 0xF>(v, -1.0));   // quad_perm [2,3,0,1]
-    v = fmax(v, dpp_d<0x114, 0xF, 0xE>(v, -1.0));  // row_shr:4
-    v = fmax(v, dpp_d<0x118, 0xF, 0xC>(v, -1.0));  // row_shr:8
-    v = fmax(v, dpp_d<0x142, 0xA, 0xF>(v, -1.0));  // row_bcast:15
-    v = fmax(v, dpp_d<0x143, 0xC, 0xF>(v, -1.0));  // row_bcast:31
+    v = max_nn(v, dpp_d<0xB1, 0xF, 0xF>(v, -1.0));   // quad_perm [1,0,3,2]
+    v = max_nn(v, dpp_d<0x4E, 0xF, 0xF>(v, -1.0));   // quad_perm [2,3,0,1]
+    v = max_nn(v, dpp_d<0x114, 0xF, 0xE>(v, -1.0));  // row_shr:4
+    v = max_nn(v, dpp_d<0x118, 0xF, 0xC>(v, -1.0));  // row_shr:8
+    v = max_nn(v, dpp_d<0x142, 0xA, 0xF>(v, -1.0));  // row_bcast:15
+    v = max_nn(v, dpp_d<0x143, 0xC, 0xF>(v, -1.0));  // row_bcast:31
     return bcast_d(v, 63);
 }
 
@@ -301,9 +303,10 @@ __attribute__((amdgpu_waves_per_eu(WPE, WPE))) k_solve(SolveArgs A) {
         constexpr int ps0 = PSB * B;
         const int k0 = g * B;
         const int cnt = (k0 + B < M) ? B : M - k0;
+        bool stop = false;
         sfor<0, B>([&](auto CI) SI {
             constexpr int c = CI;
-            if (c >= cnt || failk[g & 1] != NOFAIL) return;
+            if (c >= cnt || stop) return;
             const int kk = k0 + c;
             double best = -1.0;
             sfor<0, R>([&](auto RI) SI {
@@ -314,6 +317,7 @@ __attribute__((amdgpu_waves_per_eu(WPE, WPE))) k_solve(SolveArgs A) {
             const double m = wave_max_d(best);
             if (!(m > 0.0)) {
                 if (lane == 0) failk[g & 1] = kk;
+                stop = true;
                 return;
             }
             int p = -1;
@@ -323,11 +327,12 @@ __attribute__((amdgpu_waves_per_eu(WPE, WPE))) k_solve(SolveArgs A) {
                 if (p < 0 && msk) p = 64 * r + __ffsll((long long)msk) - 1;
             });
             const int pl = p & 63, pr = p >> 6;
-            double pv = 0.0;
-            sfor<0, R>([&](auto RI) SI {
+            double pvsel = a[0][ps0 + c];
+            sfor<1, R>([&](auto RI) SI {
                 constexpr int r = RI;
-                if (pr == r) pv = bcast_d(a[r][ps0 + c], pl);
+                pvsel = (pr == r) ? a[r][ps0 + c] : pvsel;
             });
+            const double pv = bcast_d(pvsel, pl);
             const double rinv = 1.0 / pv;
             double l[R];
             sfor<0, R>([&](auto RI) SI {
@@ -342,11 +347,12 @@ __attribute__((amdgpu_waves_per_eu(WPE, WPE))) k_solve(SolveArgs A) {
             }
             sfor<c + 1, B>([&](auto CC) SI {
                 constexpr int cc = CC;
-                double u = 0.0;
-                sfor<0, R>([&](auto RI) SI {
+                double usel = a[0][ps0 + cc];
+                sfor<1, R>([&](auto RI) SI {
                     constexpr int r = RI;
-                    if (pr == r) u = bcast_d(a[r][ps0 + cc], pl);
+                    usel = (pr == r) ? a[r][ps0 + cc] : usel;
                 });
+                const double u = bcast_d(usel, pl);
                 sfor<0, R>([&](auto RI) SI {
                     constexpr int r = RI;
                     a[r][ps0 + cc] = fma(-l[r], u, a[r][ps0 + cc]);
@@ -357,8 +363,9 @@ __attribute__((amdgpu_waves_per_eu(WPE, WPE))) k_solve(SolveArgs A) {
     // apply the rank-1 updates of block g's steps, in step order, to this
     // wave's slots S0 .. NC-1; mark the pivot rows as used and update the
     // right-hand side.  Row p's entries reach every lane by readlane.
-    auto upd = [&](auto S0C, int g, int cnt) SI {
-        constexpr int S0 = S0C;
+    auto upd = [&](auto S0C, auto S1C, auto YC, int g, int cnt) SI {
+        constexpr int S0 = S0C, S1 = S1C;
+        constexpr bool DO_Y = YC;
         const int k0 = g * B;
         for (int c = 0; c < cnt; ++c) {
             const int kk = k0 + c;
@@ -373,8 +380,8 @@ __attribute__((amdgpu_waves_per_eu(WPE, WPE))) k_solve(SolveArgs A) {
             sfor<0, R>([&](auto PRI) SI {
                 constexpr int prr = PRI;
                 if (pr == prr) {
-                    const double yp = bcast_d(y[prr], pl);
-                    sfor<S0, NC>([&](auto S) SI {
+                    const double yp = DO_Y ? bcast_d(y[prr], pl) : 0.0;
+                    sfor<S0, S1>([&](auto S) SI {
                         constexpr int sl = S;
                         const double u = bcast_d(a[prr][sl], pl);
                         sfor<0, R>([&](auto RI) SI {
@@ -385,36 +392,41 @@ __attribute__((amdgpu_waves_per_eu(WPE, WPE))) k_solve(SolveArgs A) {
                         // otherwise hoist them all and run out of registers)
                         if constexpr ((sl - S0) % 4 == 3) __builtin_amdgcn_sched_barrier(0);
                     });
-                    sfor<0, R>([&](auto RI) SI {
-                        constexpr int r = RI;
-                        y[r] = fma(-l[r], yp, y[r]);
-                    });
+                    if constexpr (DO_Y) {
+                        sfor<0, R>([&](auto RI) SI {
+                            constexpr int r = RI;
+                            y[r] = fma(-l[r], yp, y[r]);
+                        });
+                    }
                 }
             });
         }
     };
-    const int nblk = (M + B - 1) / B;
+    using YES = std::integral_constant<bool, true>;
+    using NO = std::integral_constant<bool, false>;
     bool dead = false;
-    for (int g = 0; g < nblk; ++g) {
-        const int ow = g % W, psb = g / W;  // owner wave and slot-block of block g
-        if (wv == ow) {
-            sfor<0, NCB>([&](auto SB) SI {
-                if (psb == SB) factor(SB, g);
-            });
+    // blocks g = sb * W + ow: the slot-block sb is a compile-time loop, the
+    // owner wave ow a runtime loop, so every register slot stays static
+    sfor<0, NCB>([&](auto SBC) SI {
+        constexpr int sb = SBC;
+        for (int ow = 0; ow < W; ++ow) {
+            const int g = sb * W + ow;
+            const int k0 = g * B;
+            if (dead || k0 >= M) break;
+            if (wv == ow) {
+                __builtin_amdgcn_s_setprio(2);
+                factor(SBC, g);
+                __builtin_amdgcn_s_setprio(0);
+            }
+            __syncthreads();
+            const int fa = failk[g & 1];
+            const int kend = (k0 + B < M) ? k0 + B : M;
+            const int cnt = ((kend < fa) ? kend : fa) - k0;
+            if (wv > ow) upd(std::integral_constant<int, sb * B>{}, std::integral_constant<int, NC>{}, YES{}, g, cnt);
+            else upd(std::integral_constant<int, (sb + 1) * B>{}, std::integral_constant<int, NC>{}, YES{}, g, cnt);
+            dead = (fa != NOFAIL);
         }
-        __syncthreads();
-        const int fa = failk[g & 1];
-        const int k0 = g * B;
-        const int kend = (k0 + B < M) ? k0 + B : M;
-        const int cnt = ((kend < fa) ? kend : fa) - k0;
-        const int sbA = (wv > ow) ? psb : psb + 1;  // first active slot-block of this wave
-        sfor<0, NCB + 1>([&](auto SB) SI {
-            constexpr int sb = SB;
-            if (sbA == sb) upd(std::integral_constant<int, sb * B>{}, g, cnt);
-        });
-        dead = (fa != NOFAIL);
-        if (dead) break;
-    }
+    });
     if (dead) {
         if (t == 0) {
             atomicAdd(&A.status[ST_SINGULAR], 1);
