@@ -51,7 +51,8 @@ enum {
     RBFSL_E_SINGULAR = -4,  /* a stencil system had a zero pivot (e.g. duplicate nodes) */
     RBFSL_E_NONFINITE = -5, /* a stencil produced non-finite weights */
     RBFSL_E_STATE = -6,     /* call not valid in the current state (e.g. q not set) */
-    RBFSL_E_SEARCH = -7     /* the neighbour search could not bound a stencil */
+    RBFSL_E_SEARCH = -7,    /* the neighbour search could not bound a stencil */
+    RBFSL_E_BUDGET = -8     /* a pool has no free run slot or HBM for the run */
 };
 
 /* Velocity fields u(x,t) (tangent to the sphere, divergence free).
@@ -149,6 +150,119 @@ const char *rbfsl_strerror(int code);
  * until the next call on it). */
 const char *rbfsl_last_error(const rbfsl_ctx *ctx);
 void rbfsl_destroy(rbfsl_ctx *ctx);
+
+/* ------------------------------------------------------------------------
+ * Pooled runs: the batched and served forms.
+ *
+ * A pool holds many independent transport runs (each: its own nodes, flow,
+ * stencil size n, degree L, PHS order k, tracers and step count) resident in
+ * HBM and advances all of them together.  Each step is one persistent launch
+ * per kernel family in which every node of every run goes through the whole
+ * of Algorithm 1 (departure point, stencil search, assembly and solution of
+ * the system of eq. rbf_poly_linsys, new value of q); the launches of one
+ * step are captured once as a HIP graph and replayed.  Results are bit for
+ * bit those of rbfsl_run on the same run (stencil_mode 0).
+ *
+ * Memory: the pool reserves `hbm_budget` bytes of device memory at creation
+ * and places every admitted run inside it (rbfsl_pool_run_bytes says how
+ * much one run takes); admission fails with RBFSL_E_BUDGET when no slot or no
+ * contiguous space is left.  The pool works on streams of its own; calls that
+ * return data synchronise them.  One host thread at a time per pool.
+ * ------------------------------------------------------------------------ */
+typedef struct rbfsl_pool rbfsl_pool;
+
+typedef struct {
+    int32_t max_runs;   /* run slots, 1 .. 4096                                   */
+    int32_t use_graph;  /* 1: every step is one replay of a captured HIP graph;   *
+                         * 0: the same kernels launched one by one                */
+    int64_t hbm_budget; /* bytes reserved for run state; 0: half the free memory  */
+} rbfsl_pool_config;
+
+int rbfsl_pool_create(const rbfsl_pool_config *cfg, rbfsl_pool **out);
+
+/* Device bytes one run of N nodes with these parameters and nsteps steps
+ * occupies in a pool (-1 on invalid input). */
+int64_t rbfsl_pool_run_bytes(int64_t N, const rbfsl_params *p, int64_t nsteps);
+
+/* Admit a run: N x 3 nodes, q0 (n_tracers x N), nsteps steps from p->t0.
+ * p->stencil_mode must be 0.  The run starts with the next step; *run_id
+ * names it.  RBFSL_E_BUDGET: no free slot or HBM (nothing was changed). */
+int rbfsl_pool_add(rbfsl_pool *pool, const double *nodes_xyz, int64_t N, int nodes_on_device,
+                   const rbfsl_params *p, const double *q0, int q_on_device, int64_t nsteps,
+                   int64_t *run_id);
+
+/* Up to nsteps steps of every run that has steps left; a run stops at its
+ * own step count, or at a failing step (singular/non-finite/search), which is
+ * then not committed: its q stays at that step (as rbfsl_run).  Synchronises
+ * at the end; per-run outcome through rbfsl_pool_run_info. */
+int rbfsl_pool_step(rbfsl_pool *pool, int64_t nsteps);
+
+/* Steps done, steps requested, and RBFSL_OK or the failure code of a run. */
+int rbfsl_pool_run_info(rbfsl_pool *pool, int64_t run_id, int64_t *step, int64_t *nsteps, int *status);
+
+/* q of a run at its current step (n_tracers x N). */
+int rbfsl_pool_get_q(rbfsl_pool *pool, int64_t run_id, double *out, int on_device);
+
+/* Retire a run and give its slot and memory back. */
+int rbfsl_pool_remove(rbfsl_pool *pool, int64_t run_id);
+
+typedef struct {
+    int32_t runs, active;         /* admitted runs; runs with steps left */
+    int64_t bytes_used, bytes_budget;
+    int64_t steps_launched;
+    int64_t items_per_step[3];    /* queue items of the last step, per kernel family */
+    int32_t blocks[3];            /* persistent workgroups per launch, per family    */
+    int32_t graph;
+} rbfsl_pool_stats;
+int rbfsl_pool_info(rbfsl_pool *pool, rbfsl_pool_stats *st);
+
+/* The compiled solver variants of the pooled kernels: for variant i, the
+ * largest system, waves per stencil, stencils per workgroup and panel width.
+ * Returns the number of variants (fills at most cap entries). */
+int rbfsl_pool_variants(int32_t *mcap, int32_t *waves, int32_t *group, int32_t *panel, int32_t cap);
+
+/* Use variant `variant` (-1: the default) for every run with n + (L+1)^2 = M. */
+int rbfsl_pool_set_variant(rbfsl_pool *pool, int32_t M, int32_t variant);
+
+/* Autotuner: for every system size among the runs with steps left, time
+ * `trials` uncommitted steps of those runs with each variant that can solve
+ * them and keep the fastest (results do not depend on the choice).  One entry
+ * per (size, variant) tried goes to res (at most cap; count = entries). */
+typedef struct {
+    int32_t M, variant;
+    float ms_per_step;
+    int32_t chosen;
+} rbfsl_tune_result;
+int rbfsl_pool_tune(rbfsl_pool *pool, int32_t trials, rbfsl_tune_result *res, int32_t cap, int32_t *count);
+
+/* Served form: run a stream of requests through the pool with continuous
+ * batching.  Request i arrives `arrival` seconds after the call starts; it is
+ * admitted first come first served as soon as a slot and HBM are free (while
+ * other runs are stepping), steps alongside everything else on the device,
+ * and its final q (n_tracers x N, host) is written to q_out.  Host arrays are
+ * read during the call only.  res[i]: admission and completion times (seconds
+ * after the start), RBFSL_OK or the failure code, steps done.  A request that
+ * cannot fit an empty pool gets RBFSL_E_BUDGET. */
+typedef struct {
+    double arrival;
+    const double *nodes_xyz;  /* N x 3, host */
+    int64_t N;
+    rbfsl_params params;
+    const double *q0;         /* n_tracers x N, host */
+    int64_t nsteps;
+    double *q_out;            /* n_tracers x N, host */
+} rbfsl_request;
+typedef struct {
+    double admitted, finished;
+    int32_t status;
+    int32_t pad;
+    int64_t steps;
+} rbfsl_request_result;
+int rbfsl_pool_serve(rbfsl_pool *pool, const rbfsl_request *req, int64_t nreq, rbfsl_request_result *res,
+                     double *wall_seconds);
+
+const char *rbfsl_pool_last_error(const rbfsl_pool *pool);
+void rbfsl_pool_destroy(rbfsl_pool *pool);
 
 #ifdef __cplusplus
 }

@@ -22,6 +22,7 @@ RBFSL_E_SINGULAR = -4
 RBFSL_E_NONFINITE = -5
 RBFSL_E_STATE = -6
 RBFSL_E_SEARCH = -7
+RBFSL_E_BUDGET = -8
 
 VEL_ZERO, VEL_SOLID_BODY, VEL_DEFORM = 0, 1, 2
 
@@ -30,6 +31,9 @@ EXPORTS = [
     "rbfsl_get_failures", "rbfsl_profile", "rbfsl_phase_times", "rbfsl_debug_departure", "rbfsl_debug_stencils", "rbfsl_debug_weights",
     "rbfsl_knn", "rbfsl_weights", "rbfsl_max_system", "rbfsl_strerror", "rbfsl_last_error",
     "rbfsl_destroy",
+    "rbfsl_pool_create", "rbfsl_pool_run_bytes", "rbfsl_pool_add", "rbfsl_pool_step", "rbfsl_pool_run_info",
+    "rbfsl_pool_get_q", "rbfsl_pool_remove", "rbfsl_pool_info", "rbfsl_pool_variants", "rbfsl_pool_set_variant",
+    "rbfsl_pool_tune", "rbfsl_pool_serve", "rbfsl_pool_last_error", "rbfsl_pool_destroy",
 ]
 
 
@@ -46,6 +50,33 @@ class Params(ctypes.Structure):
         ("n_tracers", ctypes.c_int32), ("vel", ctypes.c_double * 8),
         ("dt", ctypes.c_double), ("t0", ctypes.c_double),
     ]
+
+
+class PoolConfig(ctypes.Structure):
+    _fields_ = [("max_runs", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("hbm_budget", ctypes.c_int64)]
+
+
+class PoolStats(ctypes.Structure):
+    _fields_ = [("runs", ctypes.c_int32), ("active", ctypes.c_int32),
+                ("bytes_used", ctypes.c_int64), ("bytes_budget", ctypes.c_int64),
+                ("steps_launched", ctypes.c_int64), ("items_per_step", ctypes.c_int64 * 3),
+                ("blocks", ctypes.c_int32 * 3), ("graph", ctypes.c_int32)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int32), ("variant", ctypes.c_int32), ("ms_per_step", ctypes.c_float),
+                ("chosen", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("arrival", ctypes.c_double), ("nodes_xyz", ctypes.c_void_p), ("N", ctypes.c_int64),
+                ("params", Params), ("q0", ctypes.c_void_p), ("nsteps", ctypes.c_int64),
+                ("q_out", ctypes.c_void_p)]
+
+
+class RequestResult(ctypes.Structure):
+    _fields_ = [("admitted", ctypes.c_double), ("finished", ctypes.c_double), ("status", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("steps", ctypes.c_int64)]
 
 
 _lib = None
@@ -82,6 +113,25 @@ def lib():
         L.rbfsl_last_error.argtypes = [_P]
         L.rbfsl_destroy.argtypes = [_P]
         L.rbfsl_destroy.restype = None
+        L.rbfsl_pool_create.argtypes = [ctypes.POINTER(PoolConfig), ctypes.POINTER(_P)]
+        L.rbfsl_pool_run_bytes.argtypes = [i64, ctypes.POINTER(Params), i64]
+        L.rbfsl_pool_run_bytes.restype = i64
+        L.rbfsl_pool_add.argtypes = [_P, _P, i64, ctypes.c_int, ctypes.POINTER(Params), _P, ctypes.c_int, i64,
+                                     ctypes.POINTER(i64)]
+        L.rbfsl_pool_step.argtypes = [_P, i64]
+        L.rbfsl_pool_run_info.argtypes = [_P, i64, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                          ctypes.POINTER(ctypes.c_int)]
+        L.rbfsl_pool_get_q.argtypes = [_P, i64, _P, ctypes.c_int]
+        L.rbfsl_pool_remove.argtypes = [_P, i64]
+        L.rbfsl_pool_info.argtypes = [_P, ctypes.POINTER(PoolStats)]
+        L.rbfsl_pool_variants.argtypes = [_P, _P, _P, _P, i32]
+        L.rbfsl_pool_set_variant.argtypes = [_P, i32, i32]
+        L.rbfsl_pool_tune.argtypes = [_P, i32, _P, i32, ctypes.POINTER(i32)]
+        L.rbfsl_pool_serve.argtypes = [_P, _P, i64, _P, ctypes.POINTER(ctypes.c_double)]
+        L.rbfsl_pool_last_error.restype = ctypes.c_char_p
+        L.rbfsl_pool_last_error.argtypes = [_P]
+        L.rbfsl_pool_destroy.argtypes = [_P]
+        L.rbfsl_pool_destroy.restype = None
         _lib = L
     return _lib
 
@@ -111,14 +161,17 @@ def _stream(on_device):
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _check(code, ctx=None):
+def _check(code, ctx=None, pool=None):
     if code != RBFSL_OK:
         L = lib()
         msg = L.rbfsl_strerror(code).decode()
+        extra = ""
         if ctx:
             extra = L.rbfsl_last_error(ctx).decode()
-            if extra:
-                msg += ": " + extra
+        elif pool:
+            extra = L.rbfsl_pool_last_error(pool).decode()
+        if extra:
+            msg += ": " + extra
         raise RbfslError(code, msg)
 
 
@@ -261,3 +314,127 @@ def weights(nodes, idx, centers, s2, evals, n, L, k):
 
 def max_system():
     return lib().rbfsl_max_system()
+
+
+def pool_variants():
+    """Compiled solver variants of the pooled kernels: list of dicts
+    (index, mcap, waves per stencil, stencils per workgroup, panel width)."""
+    L = lib()
+    nv = L.rbfsl_pool_variants(None, None, None, None, 0)
+    a = [np.zeros(nv, dtype=np.int32) for _ in range(4)]
+    L.rbfsl_pool_variants(*[x.ctypes.data_as(_P) for x in a], nv)
+    return [dict(index=i, mcap=int(a[0][i]), waves=int(a[1][i]), group=int(a[2][i]), panel=int(a[3][i]))
+            for i in range(nv)]
+
+
+def pool_run_bytes(N, params, nsteps):
+    return int(lib().rbfsl_pool_run_bytes(int(N), ctypes.byref(params), int(nsteps)))
+
+
+class Pool:
+    """Many independent runs resident on the GPU and stepped together
+    (batched form), or fed by a request stream (served form)."""
+
+    def __init__(self, max_runs=64, hbm_budget=0, use_graph=True):
+        cfg = PoolConfig(int(max_runs), int(bool(use_graph)), int(hbm_budget))
+        self._p = _P()
+        code = lib().rbfsl_pool_create(ctypes.byref(cfg), ctypes.byref(self._p))
+        if code != RBFSL_OK:
+            self._p = None
+            _check(code)
+        self._shape = {}
+
+    def close(self):
+        if getattr(self, "_p", None):
+            lib().rbfsl_pool_destroy(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _chk(self, code):
+        _check(code, pool=self._p)
+
+    def add(self, nodes, params, q0, nsteps):
+        """Admit a run; returns its id (raises RbfslError with code RBFSL_E_BUDGET when it does not fit)."""
+        nptr, ndev, nk = _ptr(nodes, np.float64)
+        qptr, qdev, qk = _ptr(q0, np.float64)
+        rid = ctypes.c_int64()
+        self._chk(lib().rbfsl_pool_add(self._p, nptr, int(nodes.shape[0]), ndev, ctypes.byref(params), qptr, qdev,
+                                       int(nsteps), ctypes.byref(rid)))
+        self._shape[rid.value] = (params.n_tracers, int(nodes.shape[0]))
+        return rid.value
+
+    def step(self, nsteps=1):
+        self._chk(lib().rbfsl_pool_step(self._p, int(nsteps)))
+
+    def info(self, rid):
+        """(steps done, steps requested, status code) of a run."""
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int()
+        self._chk(lib().rbfsl_pool_run_info(self._p, int(rid), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def get_q(self, rid, out=None):
+        if out is None:
+            out = np.zeros(self._shape[rid])
+        ptr, dev, keep = _ptr(out, np.float64)
+        self._chk(lib().rbfsl_pool_get_q(self._p, int(rid), ptr, dev))
+        return out
+
+    def remove(self, rid):
+        self._chk(lib().rbfsl_pool_remove(self._p, int(rid)))
+        self._shape.pop(rid, None)
+
+    def stats(self):
+        st = PoolStats()
+        self._chk(lib().rbfsl_pool_info(self._p, ctypes.byref(st)))
+        return dict(runs=st.runs, active=st.active, bytes_used=st.bytes_used, bytes_budget=st.bytes_budget,
+                    steps_launched=st.steps_launched, items_per_step=list(st.items_per_step),
+                    blocks=list(st.blocks), graph=bool(st.graph))
+
+    def set_variant(self, M, variant):
+        self._chk(lib().rbfsl_pool_set_variant(self._p, int(M), int(variant)))
+
+    def tune(self, trials=2):
+        """Autotune the solver variant per system size; returns the trials."""
+        cap = 256
+        res = (TuneResult * cap)()
+        cnt = ctypes.c_int32()
+        self._chk(lib().rbfsl_pool_tune(self._p, int(trials), res, cap, ctypes.byref(cnt)))
+        return [dict(M=r.M, variant=r.variant, ms_per_step=r.ms_per_step, chosen=bool(r.chosen))
+                for r in res[:cnt.value]]
+
+    def serve(self, requests):
+        """requests: list of dicts (arrival, nodes, params, q0, nsteps).  Runs
+        the stream with continuous batching; returns (results, q_outs, wall_s)."""
+        nreq = len(requests)
+        req = (Request * max(nreq, 1))()
+        res = (RequestResult * max(nreq, 1))()
+        keep, outs = [], []
+        for i, r in enumerate(requests):
+            nodes = np.ascontiguousarray(r["nodes"], dtype=np.float64)
+            q0 = np.ascontiguousarray(r["q0"], dtype=np.float64)
+            out = np.zeros_like(q0)
+            keep += [nodes, q0]
+            outs.append(out)
+            req[i].arrival = float(r["arrival"])
+            req[i].nodes_xyz = nodes.ctypes.data
+            req[i].N = nodes.shape[0]
+            req[i].params = r["params"]
+            req[i].q0 = q0.ctypes.data
+            req[i].nsteps = int(r["nsteps"])
+            req[i].q_out = out.ctypes.data
+        wall = ctypes.c_double()
+        self._chk(lib().rbfsl_pool_serve(self._p, req, nreq, res, ctypes.byref(wall)))
+        results = [dict(admitted=res[i].admitted, finished=res[i].finished, status=res[i].status,
+                        steps=res[i].steps) for i in range(nreq)]
+        return results, outs, wall.value

@@ -94,7 +94,7 @@ void vel_coef_at(int vel_id, const double *vp, double t, VelCoef *vc) {
     vc->c = vp[4] * cos_of((M_PI * t) / T);
 }
 
-StepCoef step_coef(const rbfsl_params &p, int64_t m) {
+StepCoef make_step_coef(const rbfsl_params &p, int64_t m) {
     StepCoef sc;
     const double t1 = p.t0 + (double)(m + 1) * p.dt;
     const double tm = p.t0 + (double)m * p.dt;
@@ -139,13 +139,7 @@ hipError_t upload_points(const double *xyz, int64_t N, int on_device, double *x,
     double *tmp = nullptr;
     hipError_t e = hipMalloc(&tmp, sizeof(double) * 3 * N);
     if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(tmp, xyz, sizeof(double) * 3 * N,
-                       on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_aos_to_soa, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, tmp,
-                           N, x, y, z);
-        e = hipGetLastError();
-    }
+    e = rbfsl::upload_points_via(xyz, N, on_device, x, y, z, tmp, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(tmp);
     return e;
@@ -248,7 +242,7 @@ void prof_collect(rbfsl_ctx *c) {
 }
 
 hipError_t enqueue_step(rbfsl_ctx *c, int64_t m) {
-    const StepCoef sc = step_coef(c->p, m);
+    const StepCoef sc = make_step_coef(c->p, m);
     hipError_t e = prof_mark(c, 0);
     if (e != hipSuccess) return e;
     e = launch_trace(c->nx, c->ny, c->nz, c->N, sc, c->ex, c->ey, c->ez, c->status, m, c->stream);
@@ -281,6 +275,47 @@ hipError_t enqueue_step(rbfsl_ctx *c, int64_t m) {
 
 }  // namespace
 
+namespace rbfsl {
+
+StepCoef step_coef(const rbfsl_params &p, int64_t m) { return make_step_coef(p, m); }
+
+int validate_params(int64_t N, const rbfsl_params *p, int *L, int *k, char *msg, size_t msz) {
+    msg[0] = 0;
+    if (N < 1 || N > 0x7fffffffLL) {
+        snprintf(msg, msz, "node count N=%lld out of range", (long long)N);
+        return RBFSL_E_INVAL;
+    }
+    if (!(p->dt > 0.0) || !isfinite(p->dt) || !isfinite(p->t0) || p->n_tracers < 1) {
+        snprintf(msg, msz, "dt must be positive and finite, t0 finite, n_tracers >= 1");
+        return RBFSL_E_INVAL;
+    }
+    if (p->velocity_id < RBFSL_VEL_ZERO || p->velocity_id > RBFSL_VEL_DEFORM) {
+        snprintf(msg, msz, "unknown velocity_id %d", p->velocity_id);
+        return RBFSL_E_INVAL;
+    }
+    if (p->velocity_id != RBFSL_VEL_ZERO && (!(p->vel[0] != 0.0) || !isfinite(p->vel[0]))) {
+        snprintf(msg, msz, "the flow period vel[0] must be finite and non-zero");
+        return RBFSL_E_INVAL;
+    }
+    if (p->stencil_mode != 0 && p->stencil_mode != 1) {
+        snprintf(msg, msz, "stencil_mode must be 0 or 1");
+        return RBFSL_E_INVAL;
+    }
+    return resolve_nlk(N, p->n, p->L, p->k, L, k, msg, msz);
+}
+
+hipError_t upload_points_via(const double *xyz, int64_t N, int on_device, double *x, double *y,
+                             double *z, double *tmp, hipStream_t s) {
+    if (N == 0) return hipSuccess;
+    hipError_t e = hipMemcpyAsync(tmp, xyz, sizeof(double) * 3 * N,
+                                  on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_aos_to_soa, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, tmp, N, x, y, z);
+    return hipGetLastError();
+}
+
+}  // namespace rbfsl
+
 extern "C" {
 
 int rbfsl_max_system(void) { return MAX_SYSTEM; }
@@ -295,6 +330,7 @@ const char *rbfsl_strerror(int code) {
         case RBFSL_E_NONFINITE: return "non-finite stencil weights";
         case RBFSL_E_STATE: return "invalid state";
         case RBFSL_E_SEARCH: return "neighbour search failed";
+        case RBFSL_E_BUDGET: return "no free run slot or HBM budget";
         default: return "unknown status";
     }
 }
@@ -305,14 +341,10 @@ int rbfsl_create(const double *nodes_xyz, int64_t N, int nodes_on_device, const 
                  void *hip_stream, rbfsl_ctx **out) {
     if (!out) return RBFSL_E_INVAL;
     *out = nullptr;
-    if (!p || !nodes_xyz || N < 1 || N > 0x7fffffffLL) return RBFSL_E_INVAL;
-    if (!(p->dt > 0.0) || !isfinite(p->dt) || !isfinite(p->t0) || p->n_tracers < 1) return RBFSL_E_INVAL;
-    if (p->velocity_id < RBFSL_VEL_ZERO || p->velocity_id > RBFSL_VEL_DEFORM) return RBFSL_E_INVAL;
-    if (p->velocity_id != RBFSL_VEL_ZERO && (!(p->vel[0] != 0.0) || !isfinite(p->vel[0]))) return RBFSL_E_INVAL;
-    if (p->stencil_mode != 0 && p->stencil_mode != 1) return RBFSL_E_INVAL;
+    if (!p || !nodes_xyz) return RBFSL_E_INVAL;
     int L, k;
     char msg[256];
-    if (resolve_nlk(N, p->n, p->L, p->k, &L, &k, msg, sizeof msg) != RBFSL_OK) return RBFSL_E_INVAL;
+    if (validate_params(N, p, &L, &k, msg, sizeof msg) != RBFSL_OK) return RBFSL_E_INVAL;
     rbfsl_ctx *c = new (std::nothrow) rbfsl_ctx();
     if (!c) return RBFSL_E_NOMEM;
     c->p = *p;

@@ -82,22 +82,47 @@ __global__ void k_gather_sorted(const double *nx, const double *ny, const double
     sz[p] = nz[i];
 }
 
-hipError_t grid_build(const double *nx, const double *ny, const double *nz, int64_t N, int n,
-                      Grid *g, hipStream_t s) {
+void grid_dims(int64_t N, int n, int *G, double *invh, double *R0) {
     // First search radius: the chordal ball of radius R covers the area pi R^2
     // of the unit sphere, i.e. about N R^2 / 4 quasi-uniform nodes; aim for
     // 1.4 n of them.  Cells are R/1.5 wide, so a ball spans at most 4 cells
     // per axis.
-    double R0 = 2.0 * sqrt(1.4 * (double)n / (double)N);
-    if (R0 > 2.0) R0 = 2.0;
-    double h = R0 / 1.5;
-    int G = (int)ceil(2.0 / h);
-    if (G < 1) G = 1;
-    if (G > 160) G = 160;
-    g->G = G;
-    g->invh = (double)G / 2.0;
-    g->R0 = R0;
-    int64_t ncell = (int64_t)G * G * G;
+    double R = 2.0 * sqrt(1.4 * (double)n / (double)N);
+    if (R > 2.0) R = 2.0;
+    double h = R / 1.5;
+    int g = (int)ceil(2.0 / h);
+    if (g < 1) g = 1;
+    if (g > 160) g = 160;
+    *G = g;
+    *invh = (double)g / 2.0;
+    *R0 = R;
+}
+
+hipError_t grid_build_in(const double *nx, const double *ny, const double *nz, int64_t N, Grid *g,
+                         int *cell, int *count, hipStream_t s) {
+    const int G = g->G;
+    const int64_t ncell = (int64_t)G * G * G;
+    hipError_t e = hipMemsetAsync(count, 0, sizeof(int) * ncell, s);
+    if (e != hipSuccess) return e;
+    const unsigned bn = (unsigned)((N + 255) / 256);
+    const unsigned bc = (unsigned)((ncell + 255) / 256);
+    hipLaunchKernelGGL(k_cell_count, dim3(bn), dim3(256), 0, s, nx, ny, nz, N, G, g->invh, cell, count);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, count, ncell, g->cell_start);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(count, 0, sizeof(int) * ncell, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scatter, dim3(bn), dim3(256), 0, s, cell, N, g->cell_start, count, g->perm);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sort_cells, dim3(bc), dim3(256), 0, s, ncell, g->cell_start, g->perm);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gather_sorted, dim3(bn), dim3(256), 0, s, nx, ny, nz, N, g->perm, g->sx, g->sy, g->sz);
+    return hipGetLastError();
+}
+
+hipError_t grid_build(const double *nx, const double *ny, const double *nz, int64_t N, int n,
+                      Grid *g, hipStream_t s) {
+    grid_dims(N, n, &g->G, &g->invh, &g->R0);
+    const int64_t ncell = (int64_t)g->G * g->G * g->G;
     int *cell = nullptr, *count = nullptr;
     hipError_t e;
 #define TRY(x) do { e = (x); if (e != hipSuccess) goto fail; } while (0)
@@ -108,22 +133,7 @@ hipError_t grid_build(const double *nx, const double *ny, const double *nz, int6
     TRY(hipMalloc(&g->sx, sizeof(double) * N));
     TRY(hipMalloc(&g->sy, sizeof(double) * N));
     TRY(hipMalloc(&g->sz, sizeof(double) * N));
-    TRY(hipMemsetAsync(count, 0, sizeof(int) * ncell, s));
-    {
-        unsigned bn = (unsigned)((N + 255) / 256);
-        unsigned bc = (unsigned)((ncell + 255) / 256);
-        hipLaunchKernelGGL(k_cell_count, dim3(bn), dim3(256), 0, s, nx, ny, nz, N, G, g->invh, cell, count);
-        TRY(hipGetLastError());
-        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, count, ncell, g->cell_start);
-        TRY(hipGetLastError());
-        TRY(hipMemsetAsync(count, 0, sizeof(int) * ncell, s));
-        hipLaunchKernelGGL(k_scatter, dim3(bn), dim3(256), 0, s, cell, N, g->cell_start, count, g->perm);
-        TRY(hipGetLastError());
-        hipLaunchKernelGGL(k_sort_cells, dim3(bc), dim3(256), 0, s, ncell, g->cell_start, g->perm);
-        TRY(hipGetLastError());
-        hipLaunchKernelGGL(k_gather_sorted, dim3(bn), dim3(256), 0, s, nx, ny, nz, N, g->perm, g->sx, g->sy, g->sz);
-        TRY(hipGetLastError());
-    }
+    TRY(grid_build_in(nx, ny, nz, N, g, cell, count, s));
     TRY(hipStreamSynchronize(s));
     (void)hipFree(cell);
     (void)hipFree(count);

@@ -35,30 +35,19 @@
 #include <type_traits>
 #include <utility>
 
+#include "dev_util.h"
 #include "rbfsl_impl.h"
-
-#define SI __attribute__((always_inline))
 
 namespace rbfsl {
 
-template <int B0, typename F, int... Is>
-__device__ __forceinline__ void sfor_impl(F &&f, std::integer_sequence<int, Is...>) {
-    (f(std::integral_constant<int, B0 + Is>{}), ...);
-}
-// compile-time loop over B0..E-1 (f receives an integral_constant)
-template <int B0, int E, typename F>
-__device__ __forceinline__ void sfor(F &&f) {
-    if constexpr (E > B0) sfor_impl<B0>(f, std::make_integer_sequence<int, E - B0>{});
-}
-
-template <int W, int R, int NCB, int B, int WPE_>
+template <int W, int R, int NCB, int B, int WPE_, int CM = 24>
 struct Cfg {
     static constexpr int NT = 64 * W;
     static constexpr int ROWS = 64 * R;
     static constexpr int NC = NCB * B;                      // column slots per wave
     static constexpr int NBLK = W * NCB;                    // column blocks
     static constexpr int MCAP = (ROWS < W * NC) ? ROWS : W * NC;
-    static constexpr int CSB0 = (24 / (W * B)) > 0 ? (24 / (W * B)) : 1;  // slot-blocks per chunk
+    static constexpr int CSB0 = (CM / (W * B)) > 0 ? (CM / (W * B)) : 1;  // slot-blocks per chunk
     static constexpr int CSB = (CSB0 > NCB) ? NCB : CSB0;
     static constexpr int NCHUNK = (NCB + CSB - 1) / CSB;
     static constexpr int UBN = CSB * W * B * ROWS;          // doubles of one U chunk
@@ -70,6 +59,32 @@ struct Cfg {
     // waves per SIMD the kernel is compiled for: the compiler may use
     // 512/WPE VGPRs per lane and must not spill to reach a higher occupancy
     static constexpr int WPE = WPE_;
+};
+
+// LDS of one stencil group (W waves).  stage: assembly tables, then the panel
+// multipliers (elimination), then the U chunks (back substitution).
+template <int W, int R, int NCB, int B, int CM = 24>
+struct SolveSmem {
+    using C = Cfg<W, R, NCB, B, 1, CM>;
+    double stage[C::STAGE];
+    double rinvb[C::MCAP];
+    double zb[C::MCAP];   // the solution; its first n entries are the weights
+    int pivb[C::MCAP];
+    int failk[2];         // failing step of a panel, by block parity
+};
+
+// One stencil system: node indices S[0..n), evaluation point, centre of the
+// local frame, squared scale.  Node indices outside [0, N) are reported in
+// status (as a failed search of `step`) and read as node 0.
+struct SysIn {
+    const double *nx, *ny, *nz;
+    int64_t N;
+    const int32_t *S;
+    double xe[3], ctr[3];
+    double s2;
+    int n, L, k;
+    int *status;
+    int64_t step;
 };
 
 __device__ __forceinline__ double phs(double r2, int k) {
@@ -134,12 +149,6 @@ __device__ __forceinline__ void basis_all(int L, double al, double be, double u,
     }
 }
 
-// value of v in lane `lane` (wave-uniform), through two readlanes
-__device__ __forceinline__ double bcast_d(double v, int lane) {
-    int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-    int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-    return __hiloint2double(hi, lo);
-}
 
 template <int CTRL, int ROWM, int BANKM>
 __device__ __forceinline__ double dpp_d(double v, double ident) {
@@ -163,57 +172,41 @@ __device__ __forceinline__ double wave_max_d(double v) {
     return bcast_d(v, 63);
 }
 
-__device__ __forceinline__ void wave_lds_sync() {
-    // LDS writes by some lanes of this wave become visible to its other lanes
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
-template <int W, int R, int NCB, int B, int WPE>
-__global__ void __launch_bounds__(64 * W)
-__attribute__((amdgpu_waves_per_eu(WPE, WPE))) k_solve(SolveArgs A) {
-    using C = Cfg<W, R, NCB, B, WPE>;
+// Assembles and solves one system with the W waves of a stencil group;
+// t = thread index inside the group (0 .. 64W-1), block-wide barriers.
+// Returns false when elimination met a column with no usable pivot (the
+// system is singular to working precision); else the solution is in sh.zb.
+// LOCK: several groups of one workgroup run this in lockstep on systems of
+// the same size, so every group passes every barrier: a singular group keeps
+// going (on values that are then discarded) instead of leaving early.
+template <int W, int R, int NCB, int B, bool LOCK, int CM = 24>
+__device__ __forceinline__ bool solve_system(SolveSmem<W, R, NCB, B, CM> &sh, const int t, const SysIn &A) {
+    using C = Cfg<W, R, NCB, B, 1, CM>;
     constexpr int NT = C::NT, ROWS = C::ROWS, MCAP = C::MCAP, NC = C::NC;
-    // stage: assembly tables, then the panel multipliers (elimination), then
-    // the U chunks (back substitution)
-    __shared__ double stage[C::STAGE];
-    __shared__ double ub[W][C::UBW];     // each wave's part of the current pivot row
-    __shared__ double rinvb[MCAP];
-    __shared__ double zb[MCAP];
-    __shared__ int pivb[MCAP];
-    __shared__ int failk[2];             // failing step of a panel, by block parity
-    __shared__ int skip;
+    double *const stage = sh.stage;
+    double *const rinvb = sh.rinvb;
+    double *const zb = sh.zb;
+    int *const pivb = sh.pivb;
+    int *const failk = sh.failk;
     double(*lb)[B][ROWS] = reinterpret_cast<double(*)[B][ROWS]>(stage);  // [2][B][ROWS]
     constexpr int NOFAIL = 0x7fffffff;
 
-    const int64_t j = blockIdx.x;
-    const int t = threadIdx.x;
     const int lane = t & 63, wv = t >> 6;
-    // one read for the whole workgroup: this or an earlier step already failed
-    if (t == 0) {
-        skip = (A.status[ST_FAILSTEP] <= A.step);
+    if (t == 0) {  // read after the assembly barriers
         failk[0] = NOFAIL;
         failk[1] = NOFAIL;
     }
-    __syncthreads();
-    if (skip) return;
 
     const int n = A.n, L = A.L, k = A.k;
     const int mL = (L + 1) * (L + 1);
     const int M = n + mL;
 
     // ---- stencil, centre, scale, frame ----
-    const int64_t row = A.cidx ? (int64_t)A.cidx[j] : j;
-    const int32_t *Srow = A.S + row * n;
-    const double xe[3] = {A.ex[j], A.ey[j], A.ez[j]};
-    double ctr[3];
-    if (A.cx) {
-        ctr[0] = A.cx[row]; ctr[1] = A.cy[row]; ctr[2] = A.cz[row];
-    } else {
-        ctr[0] = xe[0]; ctr[1] = xe[1]; ctr[2] = xe[2];
-    }
-    const double s2 = A.s2[row];
+    const int32_t *Srow = A.S;
+    const double xe[3] = {A.xe[0], A.xe[1], A.xe[2]};
+    const double ctr[3] = {A.ctr[0], A.ctr[1], A.ctr[2]};
+    const double s2 = A.s2;
     const double s = (s2 > 0.0) ? sqrt(s2) : 1.0;
     const double inv_s = 1.0 / s;
     double e1[3], e2[3];
@@ -403,7 +396,6 @@ __attribute__((amdgpu_waves_per_eu(WPE, WPE))) k_solve(SolveArgs A) {
         }
     };
     using YES = std::integral_constant<bool, true>;
-    using NO = std::integral_constant<bool, false>;
     bool dead = false;
     // blocks g = sb * W + ow: the slot-block sb is a compile-time loop, the
     // owner wave ow a runtime loop, so every register slot stays static
@@ -412,7 +404,7 @@ __attribute__((amdgpu_waves_per_eu(WPE, WPE))) k_solve(SolveArgs A) {
         for (int ow = 0; ow < W; ++ow) {
             const int g = sb * W + ow;
             const int k0 = g * B;
-            if (dead || k0 >= M) break;
+            if ((!LOCK && dead) || k0 >= M) break;
             if (wv == ow) {
                 __builtin_amdgcn_s_setprio(2);
                 factor(SBC, g);
@@ -427,14 +419,7 @@ __attribute__((amdgpu_waves_per_eu(WPE, WPE))) k_solve(SolveArgs A) {
             dead = (fa != NOFAIL);
         }
     });
-    if (dead) {
-        if (t == 0) {
-            atomicAdd(&A.status[ST_SINGULAR], 1);
-            atomicMin(&A.status[ST_FAILSTEP], (int)A.step);
-            if (A.st_out) A.st_out[j] = RBFSL_E_SINGULAR;
-        }
-        return;
-    }
+    if (!LOCK && dead) return false;
 
     // ---- back substitution, chunks of CSB slot-blocks from the right ----
     // slot-blocks [sb1, sb2) of every wave cover columns [sb1*W*B, sb2*W*B);
@@ -508,10 +493,49 @@ __attribute__((amdgpu_waves_per_eu(WPE, WPE))) k_solve(SolveArgs A) {
     }
     __syncthreads();
 
+    return !dead;
+}
+
+// One workgroup of W waves per stencil (plain path): weights to w, failures
+// counted in status.
+template <int W, int R, int NCB, int B, int WPE>
+__global__ void __launch_bounds__(64 * W)
+__attribute__((amdgpu_waves_per_eu(WPE, WPE))) k_solve(SolveArgs A) {
+    __shared__ SolveSmem<W, R, NCB, B> sh;
+    __shared__ int skip;
+    const int64_t j = blockIdx.x;
+    const int t = threadIdx.x;
+    constexpr int NT = 64 * W;
+    // one read for the whole workgroup: this or an earlier step already failed
+    if (t == 0) skip = (A.status[ST_FAILSTEP] <= A.step);
+    __syncthreads();
+    if (skip) return;
+    const int n = A.n;
+    const int64_t row = A.cidx ? (int64_t)A.cidx[j] : j;
+    SysIn in;
+    in.nx = A.nx; in.ny = A.ny; in.nz = A.nz; in.N = A.N;
+    in.S = A.S + row * n;
+    in.xe[0] = A.ex[j]; in.xe[1] = A.ey[j]; in.xe[2] = A.ez[j];
+    if (A.cx) {
+        in.ctr[0] = A.cx[row]; in.ctr[1] = A.cy[row]; in.ctr[2] = A.cz[row];
+    } else {
+        in.ctr[0] = in.xe[0]; in.ctr[1] = in.xe[1]; in.ctr[2] = in.xe[2];
+    }
+    in.s2 = A.s2[row];
+    in.n = n; in.L = A.L; in.k = A.k;
+    in.status = A.status; in.step = A.step;
+    if (!solve_system<W, R, NCB, B, false>(sh, t, in)) {
+        if (t == 0) {
+            atomicAdd(&A.status[ST_SINGULAR], 1);
+            atomicMin(&A.status[ST_FAILSTEP], (int)A.step);
+            if (A.st_out) A.st_out[j] = RBFSL_E_SINGULAR;
+        }
+        return;
+    }
     // ---- weights ----
     bool bad = false;
     for (int aidx = t; aidx < n; aidx += NT) {
-        const double z = zb[aidx];
+        const double z = sh.zb[aidx];
         A.w[j * n + aidx] = z;
         if (!isfinite(z)) bad = true;
     }

@@ -53,6 +53,12 @@ hipError_t launch_trace(const double *nx, const double *ny, const double *nz, in
 
 hipError_t grid_build(const double *nx, const double *ny, const double *nz, int64_t N, int n,
                       Grid *g, hipStream_t s);
+// grid size, cell scale and first search radius for N nodes and n-point stencils
+void grid_dims(int64_t N, int n, int *G, double *invh, double *R0);
+// build into caller-owned arrays (g->G, invh, R0 and all pointers set;
+// cell: N ints, count: G^3 ints of scratch); enqueued only, no synchronisation
+hipError_t grid_build_in(const double *nx, const double *ny, const double *nz, int64_t N, Grid *g,
+                         int *cell, int *count, hipStream_t s);
 void grid_free(Grid *g);
 
 // n nearest nodes of Q query points (SoA qx,qy,qz).  idx: Q x n; d2: Q x n or
@@ -87,5 +93,14 @@ hipError_t launch_apply(const double *w, const int32_t *S, const int32_t *cidx, 
                         int64_t step, hipStream_t s);
 
 hipError_t launch_status_reset(int *status, hipStream_t s);
+
+// ---- host helpers shared by the single-run and the pooled API (api.hip) ----
+// validated (n, L, k) of a parameter set for N nodes; RBFSL_E_INVAL with a
+// message otherwise
+int validate_params(int64_t N, const rbfsl_params *p, int *L, int *k, char *msg, size_t msz);
+StepCoef step_coef(const rbfsl_params &p, int64_t m);  // p with resolved L, k
+// N x 3 AoS (host or device) -> SoA device arrays, through `tmp` (3N doubles)
+hipError_t upload_points_via(const double *xyz, int64_t N, int on_device, double *x, double *y,
+                             double *z, double *tmp, hipStream_t s);
 
 }  // namespace rbfsl

@@ -195,3 +195,38 @@ def batched_runs(count=64, seed=0, nmin=2048, nmax=65536, nsteps=256,
 
 def run_q0(run, X):
     return tracer_set(X, 8)[run["tracer"]][None, :].copy()
+
+
+def served_requests(count, rate, seed=1, nmin=4096, nmax=262144, smin=64, smax=512,
+                    pairs=((31, 3, 2), (56, 4, 2), (84, 5, 3), (120, 7, 4)), max_tracers=4):
+    """Transport requests of the served form: Poisson arrivals at `rate` per
+    second, N log-uniform in [nmin, nmax], (n, L, k) uniform over `pairs`,
+    solid body or deformational flow with random axis and period, steps
+    uniform in [smin, smax] (dt = T / steps, so every run ends at a return
+    time), 1..max_tracers tracers drawn from the eight fields."""
+    g = SplitMix64(seed)
+    reqs, t = [], 0.0
+    for r in range(count):
+        t += -math.log(1.0 - g.uniform()) / rate
+        N = int(math.floor(nmin * (nmax / nmin) ** g.uniform()))
+        n, L, k = pairs[min(int(g.uniform() * len(pairs)), len(pairs) - 1)]
+        deform = g.uniform() < 0.5
+        alpha = math.pi * g.uniform()
+        beta = 2.0 * math.pi * g.uniform()
+        T = 1.0 + 9.0 * g.uniform()
+        steps = smin + min(int(g.uniform() * (smax - smin + 1)), smax - smin)
+        ntr = 1 + min(int(g.uniform() * max_tracers), max_tracers - 1)
+        trs = [min(int(g.uniform() * 8), 7) for _ in range(ntr)]
+        ax = (math.sin(alpha) * math.cos(beta), math.sin(alpha) * math.sin(beta), math.cos(alpha))
+        if deform:
+            vel_id, vp = VEL_DEFORM, deform_vp(T, ax)
+        else:
+            vel_id, vp = VEL_SOLID, solid_body_vp(T, alpha, beta)
+        reqs.append(dict(name=f"req{r}", arrival=t, N=N, n=n, L=L, k=k, vel_id=vel_id, vp=vp,
+                         dt=T / steps, nsteps=steps, ntr=ntr, tracers=trs))
+    return reqs
+
+
+def request_q0(req, X):
+    fields = tracer_set(X, 8)
+    return np.stack([fields[i] for i in req["tracers"]])

@@ -49,3 +49,53 @@ def test_invalid_arguments_are_rejected_without_a_device():
     assert L.rbfsl_create(X.ctypes.data_as(ctypes.c_void_p), 100, 0, ctypes.byref(p2), None,
                           ctypes.byref(out)) == rb.RBFSL_E_INVAL
     assert not out.value
+
+
+def _c_layout(exprs):
+    """sizeof/offsetof values of header types, from a tiny C program built with gcc."""
+    import subprocess
+    import tempfile
+    src = '#include <stddef.h>\n#include <stdio.h>\n#include "rbfsl.h"\nint main(void){\n'
+    for e in exprs:
+        src += f'  printf("%zu\\n", (size_t)({e}));\n'
+    src += "  return 0;\n}\n"
+    with tempfile.TemporaryDirectory() as d:
+        c, exe = os.path.join(d, "l.c"), os.path.join(d, "l")
+        open(c, "w").write(src)
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        out = subprocess.check_output([exe]).decode().split()
+    return [int(v) for v in out]
+
+
+def test_struct_layouts_match_the_c_compiler():
+    exprs = ["sizeof(rbfsl_params)", "offsetof(rbfsl_params, vel)", "offsetof(rbfsl_params, dt)",
+             "sizeof(rbfsl_pool_config)", "sizeof(rbfsl_pool_stats)", "offsetof(rbfsl_pool_stats, blocks)",
+             "sizeof(rbfsl_tune_result)", "sizeof(rbfsl_request)", "offsetof(rbfsl_request, params)",
+             "offsetof(rbfsl_request, q_out)", "sizeof(rbfsl_request_result)",
+             "offsetof(rbfsl_request_result, steps)"]
+    want = [ctypes.sizeof(rb.Params), rb.Params.vel.offset, rb.Params.dt.offset,
+            ctypes.sizeof(rb.PoolConfig), ctypes.sizeof(rb.PoolStats), rb.PoolStats.blocks.offset,
+            ctypes.sizeof(rb.TuneResult), ctypes.sizeof(rb.Request), rb.Request.params.offset,
+            rb.Request.q_out.offset, ctypes.sizeof(rb.RequestResult), rb.RequestResult.steps.offset]
+    assert _c_layout(exprs) == want
+
+
+def test_pool_host_checks_without_a_device():
+    L = rb.lib()
+    out = ctypes.c_void_p()
+    assert L.rbfsl_pool_create(None, ctypes.byref(out)) == rb.RBFSL_E_INVAL
+    bad = rb.PoolConfig(0, 1, 0)
+    assert L.rbfsl_pool_create(ctypes.byref(bad), ctypes.byref(out)) == rb.RBFSL_E_INVAL
+    assert not out.value
+    assert L.rbfsl_strerror(rb.RBFSL_E_BUDGET) == b"no free run slot or HBM budget"
+    p = rb.make_params(84, 5, 3, n_tracers=2)
+    small = rb.pool_run_bytes(10000, p, 100)
+    large = rb.pool_run_bytes(40000, p, 100)
+    # nodes, sorted nodes, q ping-pong, staging: at least 104 bytes per node with two tracers
+    assert 104 * 10000 <= small < large
+    assert rb.pool_run_bytes(0, p, 100) == -1
+    vs = rb.pool_variants()
+    assert max(v["mcap"] for v in vs) >= 184
+    assert {v["waves"] for v in vs} >= {1, 2, 4}
+    for v in vs:
+        assert v["waves"] * v["group"] in (3, 4, 8)
