@@ -8,6 +8,17 @@ PHS + spherical-harmonic system, back substitution, gather-and-dot apply.
 Inputs are synthetic (spherical Fibonacci nodes, analytic flow, Gaussian
 fields) and resident in HBM before the timed region.
 
+Sections (all by default):
+  plain   -- the headline: one run, one launch sequence per step (the value);
+  batched -- 64 independent ragged runs advanced together by the pool (one
+             search pass and one persistent solve launch per kernel family
+             and step, graph-replayed, autotuned), against the same runs
+             stepped one after another on the plain path;
+  served  -- a Poisson stream of transport requests (arrival rate 0.8 x the
+             capacity calibrated on the request mix) through the pool's
+             continuous-batching loop under a 200 GB HBM budget: p50/p99
+             request latency and aggregate throughput.
+
 Prints one JSON line.  `--gpus N` with N > 1 is refused: this build runs on a
 single GPU (see the design notes on sharding).
 """
@@ -28,6 +39,11 @@ from paper_1804_01609_amd import workloads as W  # noqa: E402
 
 METRIC = "departure interpolations/sec (N x steps/s) batched vs plain; p50/p99 run latency"
 PEAK_FP64_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+
+
+def say(msg):
+    """Progress on stderr (the JSON line alone goes to stdout)."""
+    print(msg, file=sys.stderr, flush=True)
 
 
 def solve_flops(M):
@@ -94,6 +110,13 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--sections", default="plain,batched,served")
+    ap.add_argument("--batched-steps", type=int, default=24)
+    ap.add_argument("--served-requests", type=int, default=10)
+    ap.add_argument("--served-step-scale", type=float, default=0.25,
+                    help="scale of the requests' step counts (1.0: 64..512 steps)")
+    ap.add_argument("--served-load", type=float, default=0.8,
+                    help="arrival rate as a fraction of the capacity calibrated on the request mix")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run 5 device-to-device copies of BYTES (a known-size copy kernel "
                          "that calibrates the HBM byte counters) and exit")
@@ -167,9 +190,109 @@ def main():
                      "traffic": measured_traffic(args.config, M), "traffic_unit": "bytes/launch",
                      "flops_per_launch": fl, "launch_ms": solve_ms},
     }
+    say(f"plain: {value:.4g} interpolations/s, {ms_per_step:.3f} ms/step")
+    sections = set(args.sections.split(","))
+    if "batched" in sections:
+        out["batched"] = bench_batched(args.batched_steps, sync)
+        say(f"batched: {out['batched']['value']:.4g} interpolations/s "
+            f"({out['batched']['speedup_vs_plain']:.3f}x the plain path)")
+    if "served" in sections:
+        out["served"] = bench_served(args.served_requests, args.served_load, args.served_step_scale)
+        say(f"served: p50 {out['served']['p50_s']:.2f} s, p99 {out['served']['p99_s']:.2f} s")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, X, q0, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def _run_inputs(r):
+    X = W.fibonacci_nodes(r["N"])
+    p = rb.make_params(r["n"], r["L"], r["k"], 0, r["vel_id"], r["vp"], r["dt"], 0.0, r["ntr"])
+    return X, p
+
+
+def bench_batched(steps, sync):
+    """The 64-run batched workload: pool (tuned, graph-replayed) vs the same
+    runs one after another on the plain path, `steps` steps each."""
+    runs = W.batched_runs()
+    inputs = [(*_run_inputs(r), None) for r in runs]
+    inputs = [(X, p, W.run_q0(r, X)) for r, (X, p, _) in zip(runs, inputs)]
+    nodes = sum(r["N"] for r in runs)
+    with rb.Pool(max_runs=len(runs), hbm_budget=32 << 30) as pl:
+        for X, p, q0 in inputs:
+            pl.add(X, p, q0, runs[0]["nsteps"])
+        t = time.perf_counter()
+        trials = pl.tune(trials=1)
+        tune_s = time.perf_counter() - t
+        pl.step(1)  # warm-up (graph capture)
+        t = time.perf_counter()
+        pl.step(steps)
+        dt_pool = time.perf_counter() - t
+        st = pl.stats()
+    trs = []
+    for X, p, q0 in inputs:  # set-up outside the timed region, as for the pool
+        trs.append(rb.Transport(X, p))
+        trs[-1].set_q(q0)
+    sync()
+    t = time.perf_counter()
+    for tr in trs:
+        tr.run(steps)
+    sync()
+    dt_plain = time.perf_counter() - t
+    for tr in trs:
+        tr.close()
+    pool_v, plain_v = nodes * steps / dt_pool, nodes * steps / dt_plain
+    return {"workload": "c4-batched-64runs-N2048..65536-(31,3,2)/(56,4,2)/(84,5,3)-seed0",
+            "runs": len(runs), "nodes_per_step": nodes, "steps": steps,
+            "value": pool_v, "unit": "interpolations/s", "ms_per_step": 1e3 * dt_pool / steps,
+            "plain_value": plain_v, "plain_ms_per_step": 1e3 * dt_plain / steps,
+            "speedup_vs_plain": pool_v / plain_v, "graph": st["graph"], "blocks": st["blocks"],
+            "tune_s": tune_s,
+            "tuned": {str(t_["M"]): t_["variant"] for t_ in trials if t_["chosen"]}}
+
+
+def served_calibration(pairs, N=32768, steps=3):
+    """Device ns per interpolation of each (n, L, k) class, measured in the
+    pool (one run of N nodes per class, after one warm-up step)."""
+    ns = {}
+    for n, L, k in pairs:
+        X = W.fibonacci_nodes(N)
+        p = rb.make_params(n, L, k, 0, W.VEL_DEFORM, W.deform_vp(5.0), 5.0 / 256, 0.0, 1)
+        with rb.Pool(max_runs=1, hbm_budget=2 << 30) as pl:
+            pl.add(X, p, W.two_gaussians(X)[None], steps + 1)
+            pl.step(1)
+            t = time.perf_counter()
+            pl.step(steps)
+            ns[(n, L, k)] = 1e9 * (time.perf_counter() - t) / (N * steps)
+    return ns
+
+
+def bench_served(nreq, load, step_scale):
+    """Served workload: Poisson arrivals at `load` x the capacity calibrated on
+    the request mix (device time per request from per-class pool throughput),
+    continuous batching in the pool under a 200 GB HBM budget."""
+    pairs = ((31, 3, 2), (56, 4, 2), (84, 5, 3), (120, 7, 4))
+    cal = served_calibration(pairs)
+    smin, smax = max(1, int(round(64 * step_scale))), max(1, int(round(512 * step_scale)))
+    probe = W.served_requests(nreq, rate=1.0, smin=smin, smax=smax)
+    sec = float(np.mean([r["N"] * r["nsteps"] * cal[(r["n"], r["L"], r["k"])] * 1e-9 for r in probe]))
+    rate = load / sec
+    reqs = W.served_requests(nreq, rate=rate, smin=smin, smax=smax)
+    items = []
+    for r in reqs:
+        X, p = _run_inputs(r)
+        items.append(dict(arrival=r["arrival"], nodes=X, params=p, q0=W.request_q0(r, X), nsteps=r["nsteps"]))
+    with rb.Pool(max_runs=64, hbm_budget=200 * 10 ** 9) as pl:
+        res, outs, wall = pl.serve(items)
+    lat = np.array([x["finished"] - it["arrival"] for x, it in zip(res, items)])
+    ok = all(x["status"] == rb.RBFSL_OK for x in res)
+    total = sum(it["nodes"].shape[0] * it["nsteps"] for it in items)
+    return {"workload": f"c5-served-{nreq}req-N4096..262144-(31,3,2)/(56,4,2)/(84,5,3)/(120,7,4)"
+                        f"-steps{smin}..{smax}-seed1",
+            "requests": nreq, "load": load, "rate_per_s": rate, "mean_request_device_s": sec,
+            "calibration_ns_per_interp": {f"{n},{L},{k}": v for (n, L, k), v in cal.items()},
+            "all_ok": ok, "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+            "mean_s": float(lat.mean()), "wall_s": wall,
+            "value": total / wall, "unit": "interpolations/s", "hbm_budget_bytes": 200 * 10 ** 9}
 
 
 if __name__ == "__main__":
