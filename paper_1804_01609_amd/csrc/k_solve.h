@@ -163,12 +163,12 @@ __device__ __forceinline__ double dpp_d(double v, double ident) {
 __device__ __forceinline__ double max_nn(double a, double b) { return (b > a) ? b : a; }
 
 __device__ __forceinline__ double wave_max_d(double v) {
-    v = max_nn(v, dpp_d<0xB1, 0xF, 0xF>(v, -1.0));   // quad_perm [1,0,3,2]
-    v = max_nn(v, dpp_d<0x4E, 0xF, 0xF>(v, -1.0));   // quad_perm [2,3,0,1]
-    v = max_nn(v, dpp_d<0x114, 0xF, 0xE>(v, -1.0));  // row_shr:4
-    v = max_nn(v, dpp_d<0x118, 0xF, 0xC>(v, -1.0));  // row_shr:8
-    v = max_nn(v, dpp_d<0x142, 0xA, 0xF>(v, -1.0));  // row_bcast:15
-    v = max_nn(v, dpp_d<0x143, 0xC, 0xF>(v, -1.0));  // row_bcast:31
+    v = fmax(v, dpp_d<0xB1, 0xF, 0xF>(v, -1.0));   // quad_perm [1,0,3,2]
+    v = fmax(v, dpp_d<0x4E, 0xF, 0xF>(v, -1.0));   // quad_perm [2,3,0,1]
+    v = fmax(v, dpp_d<0x114, 0xF, 0xE>(v, -1.0));  // row_shr:4
+    v = fmax(v, dpp_d<0x118, 0xF, 0xC>(v, -1.0));  // row_shr:8
+    v = fmax(v, dpp_d<0x142, 0xA, 0xF>(v, -1.0));  // row_bcast:15
+    v = fmax(v, dpp_d<0x143, 0xC, 0xF>(v, -1.0));  // row_bcast:31
     return bcast_d(v, 63);
 }
 
@@ -313,6 +313,7 @@ __device__ __forceinline__ bool solve_system(SolveSmem<W, R, NCB, B, CM> &sh, co
                 stop = true;
                 return;
             }
+            const double rm = 1.0 / m;  // |pivot| = m: the reciprocal can start now
             int p = -1;
             sfor<0, R>([&](auto RI) SI {
                 constexpr int r = RI;
@@ -326,7 +327,7 @@ __device__ __forceinline__ bool solve_system(SolveSmem<W, R, NCB, B, CM> &sh, co
                 pvsel = (pr == r) ? a[r][ps0 + c] : pvsel;
             });
             const double pv = bcast_d(pvsel, pl);
-            const double rinv = 1.0 / pv;
+            const double rinv = (pv < 0.0) ? -rm : rm;  // = 1 / pv exactly
             double l[R];
             sfor<0, R>([&](auto RI) SI {
                 constexpr int r = RI;
@@ -454,32 +455,40 @@ __device__ __forceinline__ bool solve_system(SolveSmem<W, R, NCB, B, CM> &sh, co
         __syncthreads();
         if (wv == 0) {
             const int khi = (sb2 * W * B < M) ? sb2 * W * B : M;
+            double un[R];
+            sfor<0, R>([&](auto RI) SI { un[RI] = UB[(khi - 1 - c0) * ROWS + lane + 64 * RI]; });
             for (int kk = khi - 1; kk >= c0; --kk) {
+                double u[R];
+                sfor<0, R>([&](auto RI) SI { u[RI] = un[RI]; });
+                const int kn = (kk > c0) ? kk - 1 : c0;
+                sfor<0, R>([&](auto RI) SI { un[RI] = UB[(kn - c0) * ROWS + lane + 64 * RI]; });
                 const int kl = kk & 63, kt = kk >> 6;
-                int pk = 0;
-                double rk = 0.0;
-                sfor<0, KT>([&](auto TI) SI {
+                // pivot row and reciprocal of step kk (register slot kt, lane kl)
+                int pk = __builtin_amdgcn_readlane(pivr[0], kl);
+                double rk = bcast_d(rinvr[0], kl);
+                sfor<1, KT>([&](auto TI) SI {
                     constexpr int tt = TI;
-                    if (kt == tt) {
-                        pk = __builtin_amdgcn_readlane(pivr[tt], kl);
-                        rk = bcast_d(rinvr[tt], kl);
-                    }
+                    const int pt = __builtin_amdgcn_readlane(pivr[tt], kl);
+                    const double rt = bcast_d(rinvr[tt], kl);
+                    pk = (kt == tt) ? pt : pk;
+                    rk = (kt == tt) ? rt : rk;
                 });
                 const int pl = pk & 63, pr = pk >> 6;
-                double yk = 0.0;
-                sfor<0, R>([&](auto RI) SI {
+                double yk = bcast_d(y[0], pl);
+                sfor<1, R>([&](auto RI) SI {
                     constexpr int r = RI;
-                    if (pr == r) yk = bcast_d(y[r], pl);
+                    const double yr = bcast_d(y[r], pl);
+                    yk = (pr == r) ? yr : yk;
                 });
                 const double zk = yk * rk;
                 sfor<0, KT>([&](auto TI) SI {
                     constexpr int tt = TI;
-                    if (kt == tt && lane == kl) zr[tt] = zk;
+                    zr[tt] = (kt == tt && lane == kl) ? zk : zr[tt];
                 });
-                const double *ucol = UB + (kk - c0) * ROWS;
                 sfor<0, R>([&](auto RI) SI {
                     constexpr int r = RI;
-                    if (stepof[r] < kk) y[r] = fma(-ucol[lane + 64 * r], zk, y[r]);
+                    const double yn = fma(-u[r], zk, y[r]);
+                    y[r] = (stepof[r] < kk) ? yn : y[r];
                 });
             }
         }
