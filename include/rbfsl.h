@@ -62,8 +62,18 @@ enum {
  *   DEFORM:     u = x x grad psi + (2 pi/T) a x x with
  *               psi = kappa cos(pi t/T) psi0(R(t)^T x), psi0 = xyz + z^2 x/2,
  *               R(t) the rotation about a by 2 pi t/T; the flow reverses and
- *               every parcel returns to its start at t = T. */
-enum { RBFSL_VEL_ZERO = 0, RBFSL_VEL_SOLID_BODY = 1, RBFSL_VEL_DEFORM = 2 };
+ *               every parcel returns to its start at t = T.
+ *   NL2010:     the deformational flow of Section 4.2 (vel[0] = T only):
+ *               u_lambda = (10/T) cos(pi t/T) sin^2(lambda') sin(2 theta)
+ *                          + (2 pi/T) cos(theta),
+ *               u_theta  = (10/T) cos(pi t/T) sin(2 lambda') cos(theta),
+ *               lambda' = lambda - 2 pi t/T, evaluated in Cartesian form. */
+enum { RBFSL_VEL_ZERO = 0, RBFSL_VEL_SOLID_BODY = 1, RBFSL_VEL_DEFORM = 2, RBFSL_VEL_NL2010 = 3 };
+
+/* Departure-point integrators (Section 3.2): classical RK4, or Fehlberg's
+ * fifth-order formula; every stage point and the result are projected onto
+ * the sphere. */
+enum { RBFSL_RK4 = 0, RBFSL_RK5_FEHLBERG = 1 };
 
 typedef struct {
     int32_t n;            /* stencil size, 1 <= n <= N                                    */
@@ -74,6 +84,8 @@ typedef struct {
                                 of the node nearest to xi_j (Section 3.3.2)            */
     int32_t velocity_id;  /* RBFSL_VEL_*                                                  */
     int32_t n_tracers;    /* number of fields sharing each step's weights, >= 1           */
+    int32_t integrator;   /* RBFSL_RK4 (0) or RBFSL_RK5_FEHLBERG (1)                      */
+    int32_t reserved;     /* 0                                                            */
     double vel[8];        /* velocity parameters, see above                               */
     double dt;            /* time step, > 0                                               */
     double t0;            /* time of step 0                                               */

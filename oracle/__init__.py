@@ -15,7 +15,8 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _SO = os.path.join(_HERE, "liboracle.so")
 
 ORC_OK, ORC_SINGULAR, ORC_NONFINITE, ORC_INVAL = 0, 1, 2, 3
-VEL_ZERO, VEL_SOLID, VEL_DEFORM = 0, 1, 2
+VEL_ZERO, VEL_SOLID, VEL_DEFORM, VEL_NL2010 = 0, 1, 2, 3
+RK4, RK5F = 0, 1
 
 CFLAGS = ["-O2", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off", "-mfma", "-fopenmp"]
 
@@ -34,6 +35,7 @@ class Params(ctypes.Structure):
     _fields_ = [
         ("n", ctypes.c_int), ("L", ctypes.c_int), ("k", ctypes.c_int),
         ("mode", ctypes.c_int), ("vel_id", ctypes.c_int), ("ntr", ctypes.c_int),
+        ("rk", ctypes.c_int), ("reserved", ctypes.c_int),
         ("vp", ctypes.c_double * 8), ("dt", ctypes.c_double), ("t0", ctypes.c_double),
     ]
 
@@ -52,7 +54,7 @@ def lib():
         L = ctypes.CDLL(_SO)
         L.orc_threads.restype = ctypes.c_int
         L.orc_velocity.argtypes = [ctypes.c_int, _D, ctypes.c_double, _D, _D]
-        L.orc_trace.argtypes = [ctypes.c_int64, _D, ctypes.c_int, _D, ctypes.c_double,
+        L.orc_trace.argtypes = [ctypes.c_int64, _D, ctypes.c_int, _D, ctypes.c_int, ctypes.c_double,
                                 ctypes.c_double, ctypes.c_int64, _D]
         L.orc_knn.argtypes = [ctypes.c_int64, _D, ctypes.c_int64, _D, ctypes.c_int, _I32, _D]
         L.orc_gauss_solve.argtypes = [ctypes.c_int, _D, _D]
@@ -87,9 +89,10 @@ def threads():
     return lib().orc_threads()
 
 
-def make_params(n, L, k, mode=0, vel_id=VEL_ZERO, vp=(), dt=0.0, t0=0.0, ntr=1):
+def make_params(n, L, k, mode=0, vel_id=VEL_ZERO, vp=(), dt=0.0, t0=0.0, ntr=1, rk=RK4):
     p = Params()
     p.n, p.L, p.k, p.mode, p.vel_id, p.ntr = int(n), int(L), int(k), int(mode), int(vel_id), int(ntr)
+    p.rk = int(rk)
     v = list(vp) + [0.0] * (8 - len(vp))
     for i in range(8):
         p.vp[i] = float(v[i])
@@ -105,12 +108,12 @@ def velocity(vel_id, vp, t, x):
     return u
 
 
-def trace(nodes, vel_id, vp, t0, dt, m):
+def trace(nodes, vel_id, vp, t0, dt, m, rk=RK4):
     nodes = _f64(nodes)
     N = nodes.shape[0]
     vpa = _f64(list(vp) + [0.0] * (8 - len(vp)))
     xi = np.zeros((N, 3))
-    lib().orc_trace(N, _d(nodes), int(vel_id), _d(vpa), float(t0), float(dt), int(m), _d(xi))
+    lib().orc_trace(N, _d(nodes), int(vel_id), _d(vpa), int(rk), float(t0), float(dt), int(m), _d(xi))
     return xi
 
 

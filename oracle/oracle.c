@@ -10,8 +10,9 @@
  *
  * What it computes, per time step m -> m+1 (Algorithm 1, Section 3):
  *   1. departure points: the trajectory ODE (eq. sl_ode, Section 3.2) solved
- *      backward over [t_m, t_{m+1}] with classical RK4, projecting every stage
- *      point and the result orthogonally back onto the unit sphere;
+ *      backward over [t_m, t_{m+1}] with classical RK4 or Fehlberg's RK5,
+ *      projecting every stage point and the result orthogonally back onto
+ *      the unit sphere;
  *   2. stencils: the n nearest nodes of each departure point, by brute force
  *      (all N keys sorted);  the kd-tree of Section 2.2 only accelerates this;
  *   3. the augmented local interpolant (eq. rbf_poly) with PHS phi = r^(2k+1)
@@ -55,6 +56,10 @@
 #define VEL_ZERO 0
 #define VEL_SOLID 1
 #define VEL_DEFORM 2
+#define VEL_NL2010 3
+
+#define INT_RK4 0
+#define INT_RK5F 1
 
 int orc_threads(void) {
 #ifdef _OPENMP
@@ -73,6 +78,23 @@ int orc_threads(void) {
 /*   deformation:  u(x,t) = kap cos(pi t/T) R(t) u0(R(t)^T x) + Omega a x x   */
 /*                 R(t) = rotation about a by Omega t,                        */
 /*                 u0(y) = y x grad psi0(y),  psi0 = y0 y1 y2 + y2^2 y0 / 2   */
+/*   NL2010 deformational flow (Section 4.2), given there in longitude /      */
+/*   latitude components with T = vp[0], Omega = 2 pi / T,                   */
+/*   lambda' = lambda - Omega t:                                              */
+/*     u_lambda = (10/T) cos(pi t/T) sin^2(lambda') sin(2 theta)              */
+/*                + Omega cos(theta)                                          */
+/*     u_theta  = (10/T) cos(pi t/T) sin(2 lambda') cos(theta)                */
+/*   (the printed u_theta has sin(2 lambda - Omega t); read as sin(2 lambda'),*/
+/*   the cited test case's form: only then is the flow divergence free and    */
+/*   time independent in the rotating frame up to cos(pi t/T), so that it     */
+/*   returns every parcel at t = T as the section states).  Cartesian form    */
+/*   (x on the unit sphere, rho^2 = x^2 + y^2, e_lambda = (-y, x, 0)/rho,     */
+/*   e_theta = (-z x, -z y, rho^2)/rho):                                      */
+/*     u = A (-y, x, 0) + B (-z x, -z y, rho^2) + Omega e_z x x,              */
+/*     s1 = y cos(Omega t) - x sin(Omega t)   (= rho sin lambda'),            */
+/*     c1 = x cos(Omega t) + y sin(Omega t)   (= rho cos lambda'),            */
+/*     A = c 2z s1^2 / rho^2,  B = c 2 s1 c1 / rho^2,                         */
+/*     c = (10/T) cos(pi t/T).                                                */
 /* ------------------------------------------------------------------------ */
 
 /* libm cos and sin, each called on its own: a compiler may otherwise merge a
@@ -84,6 +106,7 @@ typedef struct {
     double c;      /* time factor of the deformation part */
     double R[9];   /* row-major rotation matrix R(t) */
     double w[3];   /* angular velocity Omega a */
+    double cw, sw; /* NL2010: cos and sin of Omega t */
 } vel_coef;
 
 static void vel_coef_at(int vel_id, const double *vp, double t, vel_coef *vc) {
@@ -93,6 +116,13 @@ static void vel_coef_at(int vel_id, const double *vp, double t, vel_coef *vc) {
     double T = vp[0];
     double a[3] = {vp[1], vp[2], vp[3]};
     double Om = (2.0 * M_PI) / T;
+    if (vel_id == VEL_NL2010) {
+        vc->w[2] = Om;
+        vc->c = (10.0 / T) * cos_of((M_PI * t) / T);
+        vc->cw = cos_of(Om * t);
+        vc->sw = sin_of(Om * t);
+        return;
+    }
     vc->w[0] = Om * a[0];
     vc->w[1] = Om * a[1];
     vc->w[2] = Om * a[2];
@@ -132,6 +162,17 @@ static void velocity(int vel_id, const vel_coef *vc, const double x[3], double u
     double wx[3];
     cross(vc->w, x, wx);
     if (vel_id == VEL_SOLID) { u[0] = wx[0]; u[1] = wx[1]; u[2] = wx[2]; return; }
+    if (vel_id == VEL_NL2010) {
+        double rho2 = x[0] * x[0] + x[1] * x[1];
+        double s1 = x[1] * vc->cw - x[0] * vc->sw;
+        double c1 = x[0] * vc->cw + x[1] * vc->sw;
+        double A = (vc->c * ((2.0 * x[2]) * (s1 * s1))) / rho2;
+        double B = (vc->c * ((2.0 * s1) * c1)) / rho2;
+        u[0] = (-(A * x[1]) - B * (x[2] * x[0])) + wx[0];
+        u[1] = (A * x[0] - B * (x[2] * x[1])) + wx[1];
+        u[2] = B * rho2 + wx[2];
+        return;
+    }
     const double *R = vc->R;
     double y[3], v[3];
     for (int i = 0; i < 3; ++i)  /* y = R^T x */
@@ -158,45 +199,91 @@ static void project(double v[3]) {
     v[2] = v[2] / r;
 }
 
-/* Departure point of node x for step m -> m+1 (eq. sl_ode backward over
- * [t_m, t_{m+1}], RK4, projection of every stage point and of the result). */
-static void departure(int vel_id, const vel_coef *c1, const vel_coef *ch, const vel_coef *c0,
-                      double dt, const double x[3], double xi[3]) {
-    double h = -dt, hh = 0.5 * h, h6 = h / 6.0;
-    double k1[3], k2[3], k3[3], k4[3], y[3];
-    velocity(vel_id, c1, x, k1);
-    for (int i = 0; i < 3; ++i) y[i] = x[i] + hh * k1[i];
-    project(y);
-    velocity(vel_id, ch, y, k2);
-    for (int i = 0; i < 3; ++i) y[i] = x[i] + hh * k2[i];
-    project(y);
-    velocity(vel_id, ch, y, k3);
-    for (int i = 0; i < 3; ++i) y[i] = x[i] + h * k3[i];
-    project(y);
-    velocity(vel_id, c0, y, k4);
+/* Fehlberg's fifth-order Runge-Kutta formula (the higher-order member of
+ * his 4(5) pair, the integrator the paper settles on in Section 3.2): stage
+ * fractions c_s, coefficients a_sj and fifth-order weights b_j, each written
+ * as the rational number it is. */
+static const double RKF_C[6] = {0.0, 1.0 / 4.0, 3.0 / 8.0, 12.0 / 13.0, 1.0, 1.0 / 2.0};
+static const double RKF_A[6][5] = {
+    {0.0, 0.0, 0.0, 0.0, 0.0},
+    {1.0 / 4.0, 0.0, 0.0, 0.0, 0.0},
+    {3.0 / 32.0, 9.0 / 32.0, 0.0, 0.0, 0.0},
+    {1932.0 / 2197.0, -7200.0 / 2197.0, 7296.0 / 2197.0, 0.0, 0.0},
+    {439.0 / 216.0, -8.0, 3680.0 / 513.0, -845.0 / 4104.0, 0.0},
+    {-8.0 / 27.0, 2.0, -3544.0 / 2565.0, 1859.0 / 4104.0, -11.0 / 40.0}};
+static const double RKF_B[6] = {16.0 / 135.0, 0.0, 6656.0 / 12825.0, 28561.0 / 56430.0, -9.0 / 50.0,
+                                2.0 / 55.0};
+
+/* velocity coefficients of every stage time of step m -> m+1 */
+typedef struct {
+    int rk;
+    vel_coef v[6];
+} step_coefs;
+
+static void step_coefs_at(int vel_id, const double *vp, int rk, double t0, double dt, int64_t m,
+                          step_coefs *sc) {
+    double t1 = t0 + (double)(m + 1) * dt;
+    sc->rk = rk;
+    if (rk == INT_RK4) {
+        vel_coef_at(vel_id, vp, t1, &sc->v[0]);
+        vel_coef_at(vel_id, vp, t1 - 0.5 * dt, &sc->v[1]);
+        vel_coef_at(vel_id, vp, t0 + (double)m * dt, &sc->v[2]);
+    } else {
+        double h = -dt;
+        for (int st = 0; st < 6; ++st) vel_coef_at(vel_id, vp, t1 + RKF_C[st] * h, &sc->v[st]);
+    }
+}
+
+/* Departure point of node x for step m -> m+1: eq. sl_ode backward over
+ * [t_m, t_{m+1}] (h = -dt from t_{m+1}), with classical RK4 or Fehlberg's
+ * RK5, every stage point and the result projected onto the sphere. */
+static void departure(int vel_id, const step_coefs *sc, double dt, const double x[3], double xi[3]) {
+    double h = -dt;
+    if (sc->rk == INT_RK4) {
+        double hh = 0.5 * h, h6 = h / 6.0;
+        double k1[3], k2[3], k3[3], k4[3], y[3];
+        velocity(vel_id, &sc->v[0], x, k1);
+        for (int i = 0; i < 3; ++i) y[i] = x[i] + hh * k1[i];
+        project(y);
+        velocity(vel_id, &sc->v[1], y, k2);
+        for (int i = 0; i < 3; ++i) y[i] = x[i] + hh * k2[i];
+        project(y);
+        velocity(vel_id, &sc->v[1], y, k3);
+        for (int i = 0; i < 3; ++i) y[i] = x[i] + h * k3[i];
+        project(y);
+        velocity(vel_id, &sc->v[2], y, k4);
+        for (int i = 0; i < 3; ++i) {
+            double s = ((k1[i] + 2.0 * k2[i]) + 2.0 * k3[i]) + k4[i];
+            xi[i] = x[i] + h6 * s;
+        }
+        project(xi);
+        return;
+    }
+    double k[6][3], y[3];
+    velocity(vel_id, &sc->v[0], x, k[0]);
+    for (int st = 1; st < 6; ++st) {
+        for (int i = 0; i < 3; ++i) {
+            double acc = RKF_A[st][0] * k[0][i];
+            for (int j = 1; j < st; ++j) acc = acc + RKF_A[st][j] * k[j][i];
+            y[i] = x[i] + h * acc;
+        }
+        project(y);
+        velocity(vel_id, &sc->v[st], y, k[st]);
+    }
     for (int i = 0; i < 3; ++i) {
-        double s = ((k1[i] + 2.0 * k2[i]) + 2.0 * k3[i]) + k4[i];
-        xi[i] = x[i] + h6 * s;
+        double acc = RKF_B[0] * k[0][i];
+        for (int j = 1; j < 6; ++j) acc = acc + RKF_B[j] * k[j][i];
+        xi[i] = x[i] + h * acc;
     }
     project(xi);
 }
 
-static void step_times(double t0, double dt, int64_t m, double *t1, double *th, double *tm) {
-    *t1 = t0 + (double)(m + 1) * dt;
-    *tm = t0 + (double)m * dt;
-    *th = *t1 - 0.5 * dt;
-}
-
-void orc_trace(int64_t N, const double *nodes, int vel_id, const double *vp,
+void orc_trace(int64_t N, const double *nodes, int vel_id, const double *vp, int rk,
                double t0, double dt, int64_t m, double *xi) {
-    double t1, th, tm;
-    step_times(t0, dt, m, &t1, &th, &tm);
-    vel_coef c1, ch, c0;
-    vel_coef_at(vel_id, vp, t1, &c1);
-    vel_coef_at(vel_id, vp, th, &ch);
-    vel_coef_at(vel_id, vp, tm, &c0);
+    step_coefs sc;
+    step_coefs_at(vel_id, vp, rk, t0, dt, m, &sc);
 #pragma omp parallel for schedule(static)
-    for (int64_t j = 0; j < N; ++j) departure(vel_id, &c1, &ch, &c0, dt, nodes + 3 * j, xi + 3 * j);
+    for (int64_t j = 0; j < N; ++j) departure(vel_id, &sc, dt, nodes + 3 * j, xi + 3 * j);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -419,15 +506,16 @@ int orc_weights(int n, int L, int k, const double *xs, const double *c, double s
 
 typedef struct {
     int n, L, k, mode, vel_id, ntr;
+    int rk; /* INT_RK4 or INT_RK5F */
+    int reserved;
     double vp[8];
     double dt, t0;
 } orc_params;
 
-static int step_one(int64_t N, const double *nodes, const orc_params *p, const vel_coef *c1,
-                    const vel_coef *ch, const vel_coef *c0, int64_t j, key_t_ *scratch,
-                    double *xs, double *xi, int32_t *S, double *w) {
+static int step_one(int64_t N, const double *nodes, const orc_params *p, const step_coefs *sc,
+                    int64_t j, key_t_ *scratch, double *xs, double *xi, int32_t *S, double *w) {
     int n = p->n;
-    departure(p->vel_id, c1, ch, c0, p->dt, nodes + 3 * j, xi);
+    departure(p->vel_id, sc, p->dt, nodes + 3 * j, xi);
     double ctr[3], s2;
     double *d2 = (double *)malloc(sizeof(double) * (size_t)n);
     if (p->mode == 0) {
@@ -458,12 +546,8 @@ static double apply_one(int n, const double *w, const int32_t *S, const double *
 int orc_step_sample(int64_t N, const double *nodes, const orc_params *p, int64_t m,
                     int64_t J, const int64_t *jl, const double *q_in, double *xi_out,
                     int32_t *S_out, double *w_out, double *q_out, int32_t *st_out) {
-    double t1, th, tm;
-    step_times(p->t0, p->dt, m, &t1, &th, &tm);
-    vel_coef c1, ch, c0;
-    vel_coef_at(p->vel_id, p->vp, t1, &c1);
-    vel_coef_at(p->vel_id, p->vp, th, &ch);
-    vel_coef_at(p->vel_id, p->vp, tm, &c0);
+    step_coefs sc;
+    step_coefs_at(p->vel_id, p->vp, p->rk, p->t0, p->dt, m, &sc);
     int n = p->n;
     int bad = 0;
 #pragma omp parallel reduction(+ : bad)
@@ -475,7 +559,7 @@ int orc_step_sample(int64_t N, const double *nodes, const orc_params *p, int64_t
 #pragma omp for schedule(dynamic, 8)
         for (int64_t t = 0; t < J; ++t) {
             double xi[3];
-            int st = step_one(N, nodes, p, &c1, &ch, &c0, jl[t], scratch, xs, xi, S, w);
+            int st = step_one(N, nodes, p, &sc, jl[t], scratch, xs, xi, S, w);
             if (st) bad += 1;
             if (st_out) st_out[t] = st;
             if (xi_out) memcpy(xi_out + 3 * t, xi, sizeof(xi));

@@ -80,6 +80,13 @@ void vel_coef_at(int vel_id, const double *vp, double t, VelCoef *vc) {
     const double T = vp[0];
     const double a[3] = {vp[1], vp[2], vp[3]};
     const double Om = (2.0 * M_PI) / T;
+    if (vel_id == RBFSL_VEL_NL2010) {
+        vc->w[2] = Om;
+        vc->c = (10.0 / T) * cos_of((M_PI * t) / T);
+        vc->cw = cos_of(Om * t);
+        vc->sw = sin_of(Om * t);
+        return;
+    }
     for (int i = 0; i < 3; ++i) vc->w[i] = Om * a[i];
     if (vel_id != RBFSL_VEL_DEFORM) return;
     const double th = Om * t;
@@ -96,16 +103,20 @@ void vel_coef_at(int vel_id, const double *vp, double t, VelCoef *vc) {
 
 StepCoef make_step_coef(const rbfsl_params &p, int64_t m) {
     StepCoef sc;
+    memset(&sc, 0, sizeof sc);
     const double t1 = p.t0 + (double)(m + 1) * p.dt;
-    const double tm = p.t0 + (double)m * p.dt;
-    const double th = t1 - 0.5 * p.dt;
-    vel_coef_at(p.velocity_id, p.vel, t1, &sc.c1);
-    vel_coef_at(p.velocity_id, p.vel, th, &sc.ch);
-    vel_coef_at(p.velocity_id, p.vel, tm, &sc.c0);
     sc.h = -p.dt;
     sc.hh = 0.5 * sc.h;
     sc.h6 = sc.h / 6.0;
     sc.vel_id = p.velocity_id;
+    sc.rk = p.integrator;
+    if (p.integrator == RBFSL_RK4) {
+        vel_coef_at(p.velocity_id, p.vel, t1, &sc.v[0]);
+        vel_coef_at(p.velocity_id, p.vel, t1 - 0.5 * p.dt, &sc.v[1]);
+        vel_coef_at(p.velocity_id, p.vel, p.t0 + (double)m * p.dt, &sc.v[2]);
+    } else {
+        for (int s = 0; s < 6; ++s) vel_coef_at(p.velocity_id, p.vel, t1 + kRk5C[s] * sc.h, &sc.v[s]);
+    }
     return sc;
 }
 
@@ -289,7 +300,7 @@ int validate_params(int64_t N, const rbfsl_params *p, int *L, int *k, char *msg,
         snprintf(msg, msz, "dt must be positive and finite, t0 finite, n_tracers >= 1");
         return RBFSL_E_INVAL;
     }
-    if (p->velocity_id < RBFSL_VEL_ZERO || p->velocity_id > RBFSL_VEL_DEFORM) {
+    if (p->velocity_id < RBFSL_VEL_ZERO || p->velocity_id > RBFSL_VEL_NL2010) {
         snprintf(msg, msz, "unknown velocity_id %d", p->velocity_id);
         return RBFSL_E_INVAL;
     }
@@ -299,6 +310,10 @@ int validate_params(int64_t N, const rbfsl_params *p, int *L, int *k, char *msg,
     }
     if (p->stencil_mode != 0 && p->stencil_mode != 1) {
         snprintf(msg, msz, "stencil_mode must be 0 or 1");
+        return RBFSL_E_INVAL;
+    }
+    if (p->integrator != RBFSL_RK4 && p->integrator != RBFSL_RK5_FEHLBERG) {
+        snprintf(msg, msz, "integrator must be RBFSL_RK4 or RBFSL_RK5_FEHLBERG");
         return RBFSL_E_INVAL;
     }
     return resolve_nlk(N, p->n, p->L, p->k, L, k, msg, msz);

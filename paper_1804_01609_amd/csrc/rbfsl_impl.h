@@ -18,15 +18,35 @@ struct VelCoef {
     double c;
     double R[9];  // row-major
     double w[3];
+    double cw, sw;  // NL2010 flow: cos and sin of (2 pi/T) t
 };
 
-// Everything one step's tracer needs: coefficients at t_{m+1}, the midpoint
-// t_{m+1} - dt/2 and t_m, and the RK4 step fractions of h = -dt.
+// Everything one step's tracer needs: the velocity coefficients at the stage
+// times (RK4: t_{m+1}, t_{m+1} - dt/2, t_m; RK5: t_{m+1} + c_s h, s = 0..5)
+// and the step h = -dt with RK4's fractions of it.
 struct StepCoef {
-    VelCoef c1, ch, c0;
+    VelCoef v[6];
     double h, hh, h6;
     int vel_id;
+    int rk;  // RBFSL_RK4 or RBFSL_RK5_FEHLBERG
 };
+
+// Fehlberg's fifth-order formula (Section 3.2): stage fractions c_s of the
+// step, stage coefficients a_sj and fifth-order weights b_j, each written as
+// the rational number it is (folded to the nearest double at compile time).
+constexpr double kRk5C[6] = {0.0, 1.0 / 4.0, 3.0 / 8.0, 12.0 / 13.0, 1.0, 1.0 / 2.0};
+struct Rk5Tableau {
+    double a[6][5];
+    double b[6];
+};
+constexpr Rk5Tableau kRk5 = {
+    {{0.0, 0.0, 0.0, 0.0, 0.0},
+     {1.0 / 4.0, 0.0, 0.0, 0.0, 0.0},
+     {3.0 / 32.0, 9.0 / 32.0, 0.0, 0.0, 0.0},
+     {1932.0 / 2197.0, -7200.0 / 2197.0, 7296.0 / 2197.0, 0.0, 0.0},
+     {439.0 / 216.0, -8.0, 3680.0 / 513.0, -845.0 / 4104.0, 0.0},
+     {-8.0 / 27.0, 2.0, -3544.0 / 2565.0, 1859.0 / 4104.0, -11.0 / 40.0}},
+    {16.0 / 135.0, 0.0, 6656.0 / 12825.0, 28561.0 / 56430.0, -9.0 / 50.0, 2.0 / 55.0}};
 
 // Spatial hash over the cube [-1,1]^3 with G cells per axis.
 struct Grid {

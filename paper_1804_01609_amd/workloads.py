@@ -14,7 +14,8 @@ import math
 
 import numpy as np
 
-VEL_ZERO, VEL_SOLID, VEL_DEFORM = 0, 1, 2
+VEL_ZERO, VEL_SOLID, VEL_DEFORM, VEL_NL2010 = 0, 1, 2, 3
+RK4, RK5F = 0, 1
 
 # the two bell centres of the deformational-flow test (Section 4.2)
 P1 = (math.sqrt(3.0) / 2.0, 0.5, 0.0)
@@ -115,6 +116,17 @@ def deform_vp(T=5.0, axis=(0.0, 0.0, 1.0), kappa=2.0):
     a = np.asarray(axis, dtype=np.float64)
     a = a / np.linalg.norm(a)
     return [float(T), float(a[0]), float(a[1]), float(a[2]), float(kappa), 0.0, 0.0, 0.0]
+
+
+def nl2010_vp(T=5.0):
+    """The NL2010 deformational flow of Section 4.2 (rotation about e_z with
+    period T; the flow reverses at T/2 and returns every parcel at T)."""
+    return [float(T), 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0]
+
+
+def gaussian_bells(X):
+    """0.95 (exp(-5|x - p1|^2) + exp(-5|x - p2|^2)): the smooth pair of Section 4.2."""
+    return 0.95 * (gaussian_bump(X, P1, 1.0 / math.sqrt(5.0)) + gaussian_bump(X, P2, 1.0 / math.sqrt(5.0)))
 
 
 def paper_L(n):

@@ -27,9 +27,9 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_params_struct_layout_matches_header():
-    # 6 int32 + 8 doubles + 2 doubles, naturally aligned
-    assert ctypes.sizeof(rb.Params) == 6 * 4 + 10 * 8
-    assert rb.Params.vel.offset == 24
+    # 8 int32 + 8 doubles + 2 doubles, naturally aligned
+    assert ctypes.sizeof(rb.Params) == 8 * 4 + 10 * 8
+    assert rb.Params.vel.offset == 32
 
 
 def test_invalid_arguments_are_rejected_without_a_device():
