@@ -85,7 +85,10 @@ typedef struct {
     int32_t velocity_id;  /* RBFSL_VEL_*                                                  */
     int32_t n_tracers;    /* number of fields sharing each step's weights, >= 1           */
     int32_t integrator;   /* RBFSL_RK4 (0) or RBFSL_RK5_FEHLBERG (1)                      */
-    int32_t reserved;     /* 0                                                            */
+    int32_t cache_factors; /* stencil_mode 1 only: 1 = factor every node's system once at
+                              create and reuse the factorizations each step (Section
+                              3.3.2; N (n+(L+1)^2)^2 doubles of device memory, results
+                              unchanged); 0 = assemble and factor every step          */
     double vel[8];        /* velocity parameters, see above                               */
     double dt;            /* time step, > 0                                               */
     double t0;            /* time of step 0                                               */

@@ -48,7 +48,7 @@ class Params(ctypes.Structure):
     _fields_ = [
         ("n", ctypes.c_int32), ("L", ctypes.c_int32), ("k", ctypes.c_int32),
         ("stencil_mode", ctypes.c_int32), ("velocity_id", ctypes.c_int32),
-        ("n_tracers", ctypes.c_int32), ("integrator", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("n_tracers", ctypes.c_int32), ("integrator", ctypes.c_int32), ("cache_factors", ctypes.c_int32),
         ("vel", ctypes.c_double * 8),
         ("dt", ctypes.c_double), ("t0", ctypes.c_double),
     ]
@@ -178,11 +178,12 @@ def _check(code, ctx=None, pool=None):
 
 
 def make_params(n, L=-1, k=-1, stencil_mode=0, velocity_id=VEL_ZERO, vel=(), dt=0.1, t0=0.0,
-                n_tracers=1, integrator=RK4):
+                n_tracers=1, integrator=RK4, cache_factors=0):
     p = Params()
     p.n, p.L, p.k = int(n), int(L), int(k)
     p.stencil_mode, p.velocity_id, p.n_tracers = int(stencil_mode), int(velocity_id), int(n_tracers)
     p.integrator = int(integrator)
+    p.cache_factors = int(cache_factors)
     v = list(vel) + [0.0] * (8 - len(vel))
     for i in range(8):
         p.vel[i] = float(v[i])

@@ -27,6 +27,10 @@ struct rbfsl_ctx {
     double *s2 = nullptr;
     int32_t *cidx = nullptr;                             // mode 1: nearest node of xi_j
     double *w = nullptr;
+    // mode 1 with cached factors: every node's factorization (Section 3.3.2)
+    bool cached = false;
+    double *F = nullptr, *frinv = nullptr;
+    int32_t *fpiv = nullptr, *fstep = nullptr, *fstat = nullptr;
     double *q[2] = {nullptr, nullptr};
     int cur = 0;
     int *status = nullptr;
@@ -208,7 +212,7 @@ void ctx_free(rbfsl_ctx *c) {
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     c->ev.clear();
     void *bufs[] = {c->nx, c->ny, c->nz, c->ex, c->ey, c->ez, c->S, c->s2, c->cidx, c->w,
-                    c->q[0], c->q[1], c->status};
+                    c->q[0], c->q[1], c->status, c->F, c->frinv, c->fpiv, c->fstep, c->fstat};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     grid_free(&c->grid);
@@ -275,7 +279,18 @@ hipError_t enqueue_step(rbfsl_ctx *c, int64_t m) {
     a.S = c->S; a.s2 = c->s2;
     a.count = c->N; a.n = c->n; a.L = c->L; a.k = c->k;
     a.w = c->w; a.st_out = nullptr; a.status = c->status; a.step = m;
-    e = launch_solve(a, c->stream);
+    if (c->cached) {
+        CachedArgs ca{};
+        ca.nx = c->nx; ca.ny = c->ny; ca.nz = c->nz; ca.N = c->N;
+        ca.ex = c->ex; ca.ey = c->ey; ca.ez = c->ez;
+        ca.S = c->S; ca.cidx = c->cidx; ca.s2 = c->s2;
+        ca.F = c->F; ca.rinv = c->frinv; ca.piv = c->fpiv; ca.stepof = c->fstep; ca.fstat = c->fstat;
+        ca.count = c->N; ca.n = c->n; ca.L = c->L; ca.k = c->k;
+        ca.w = c->w; ca.status = c->status; ca.step = m;
+        e = launch_solve_cached(ca, c->stream);
+    } else {
+        e = launch_solve(a, c->stream);
+    }
     if (e != hipSuccess) return e;
     if ((e = prof_mark(c, 3)) != hipSuccess) return e;
     e = launch_apply(c->w, c->S, c->mode == 1 ? c->cidx : nullptr, c->N, c->n, c->ntr,
@@ -314,6 +329,10 @@ int validate_params(int64_t N, const rbfsl_params *p, int *L, int *k, char *msg,
     }
     if (p->integrator != RBFSL_RK4 && p->integrator != RBFSL_RK5_FEHLBERG) {
         snprintf(msg, msz, "integrator must be RBFSL_RK4 or RBFSL_RK5_FEHLBERG");
+        return RBFSL_E_INVAL;
+    }
+    if (p->cache_factors != 0 && (p->cache_factors != 1 || p->stencil_mode != 1)) {
+        snprintf(msg, msz, "cache_factors = 1 needs stencil_mode 1 (fixed per-node systems)");
         return RBFSL_E_INVAL;
     }
     return resolve_nlk(N, p->n, p->L, p->k, L, k, msg, msz);
@@ -386,6 +405,27 @@ int rbfsl_create(const double *nodes_xyz, int64_t N, int nodes_on_device, const 
     if (e == hipSuccess && c->mode == 1) {
         // every node's own stencil, found once (the nodes do not move)
         e = launch_knn(c->grid, N, c->nx, c->ny, c->nz, N, c->n, c->S, nullptr, c->s2, c->status, 0, c->stream);
+        if (e == hipSuccess && p->cache_factors) {
+            // every node's system depends only on the node: factor each once
+            c->cached = true;
+            const size_t M = (size_t)c->M;
+            void **fb[] = {(void **)&c->F, (void **)&c->frinv, (void **)&c->fpiv, (void **)&c->fstep,
+                           (void **)&c->fstat};
+            const size_t fs[] = {d * N * M * M, d * N * M, sizeof(int32_t) * N * M, sizeof(int32_t) * N * M,
+                                 sizeof(int32_t) * N};
+            for (int b = 0; b < 5 && e == hipSuccess; ++b) e = hipMalloc(fb[b], fs[b]);
+            if (e == hipSuccess) {
+                FactorArgs fa{};
+                fa.s.nx = c->nx; fa.s.ny = c->ny; fa.s.nz = c->nz; fa.s.N = N;
+                fa.s.ex = c->nx; fa.s.ey = c->ny; fa.s.ez = c->nz;
+                fa.s.cx = c->nx; fa.s.cy = c->ny; fa.s.cz = c->nz;
+                fa.s.S = c->S; fa.s.s2 = c->s2; fa.s.cidx = nullptr;
+                fa.s.count = N; fa.s.n = c->n; fa.s.L = c->L; fa.s.k = c->k;
+                fa.s.w = nullptr; fa.s.st_out = nullptr; fa.s.status = c->status; fa.s.step = 0;
+                fa.F = c->F; fa.piv = c->fpiv; fa.rinv = c->frinv; fa.stepof = c->fstep; fa.fstat = c->fstat;
+                e = launch_factor(fa, c->stream);
+            }
+        }
         int st[ST_WORDS];
         if (e == hipSuccess) e = hipMemcpyAsync(st, c->status, sizeof st, hipMemcpyDeviceToHost, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);

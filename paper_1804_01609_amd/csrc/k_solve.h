@@ -87,6 +87,17 @@ struct SysIn {
     int64_t step;
 };
 
+// Where a factorization goes (factor-only mode): the eliminated matrix,
+// column-major M x M (rows not yet pivoted at step k hold, in column k, the
+// value that step divided by the pivot; the others hold U), the pivot row
+// and reciprocal of every step, and the step at which every row was pivoted.
+struct FactorOut {
+    double *F;
+    int32_t *piv;
+    double *rinv;
+    int32_t *stepof;
+};
+
 __device__ __forceinline__ double phs(double r2, int k) {
     double p = sqrt(r2);
     for (int t = 0; t < k; ++t) p = p * r2;
@@ -180,8 +191,9 @@ __device__ __forceinline__ double wave_max_d(double v) {
 // LOCK: several groups of one workgroup run this in lockstep on systems of
 // the same size, so every group passes every barrier: a singular group keeps
 // going (on values that are then discarded) instead of leaving early.
-template <int W, int R, int NCB, int B, bool LOCK, int CM = 24>
-__device__ __forceinline__ bool solve_system(SolveSmem<W, R, NCB, B, CM> &sh, const int t, const SysIn &A) {
+template <int W, int R, int NCB, int B, bool LOCK, int CM = 24, bool FACT = false>
+__device__ __forceinline__ bool solve_system(SolveSmem<W, R, NCB, B, CM> &sh, const int t, const SysIn &A,
+                                             const FactorOut *fo = nullptr) {
     using C = Cfg<W, R, NCB, B, 1, CM>;
     constexpr int NT = C::NT, ROWS = C::ROWS, MCAP = C::MCAP, NC = C::NC;
     double *const stage = sh.stage;
@@ -422,6 +434,33 @@ __device__ __forceinline__ bool solve_system(SolveSmem<W, R, NCB, B, CM> &sh, co
     });
     if (!LOCK && dead) return false;
 
+    if constexpr (FACT) {
+        // factor-only mode: store the factorization instead of solving
+        sfor<0, NC>([&](auto S) SI {
+            constexpr int sl = S;
+            const int jc = ((sl / B) * W + wv) * B + sl % B;
+            if (jc < M) {
+                sfor<0, R>([&](auto RI) SI {
+                    constexpr int r = RI;
+                    const int i = lane + 64 * r;
+                    if (i < M) fo->F[(int64_t)jc * M + i] = a[r][sl];
+                });
+            }
+        });
+        if (wv == 0) {
+            sfor<0, R>([&](auto RI) SI {
+                constexpr int r = RI;
+                const int i = lane + 64 * r;
+                if (i < M) fo->stepof[i] = stepof[r];
+            });
+        }
+        for (int kk = t; kk < M; kk += NT) {
+            fo->piv[kk] = pivb[kk];
+            fo->rinv[kk] = rinvb[kk];
+        }
+        return true;
+    }
+
     // ---- back substitution, chunks of CSB slot-blocks from the right ----
     // slot-blocks [sb1, sb2) of every wave cover columns [sb1*W*B, sb2*W*B);
     // wave 0 holds the pivots and reciprocals in registers (lane k % 64)
@@ -556,6 +595,46 @@ __attribute__((amdgpu_waves_per_eu(WPE, WPE))) k_solve(SolveArgs A) {
         }
         if (A.st_out) A.st_out[j] = anybad ? RBFSL_E_NONFINITE : 0;
     }
+}
+
+// One workgroup per stencil: assemble and eliminate, store the factorization
+// (row t of FactorArgs' arrays) instead of solving; fstat[t] = 0, or
+// RBFSL_E_SINGULAR when the system has no usable pivot.
+template <int W, int R, int NCB, int B, int WPE>
+__global__ void __launch_bounds__(64 * W)
+__attribute__((amdgpu_waves_per_eu(WPE, WPE))) k_factor(FactorArgs FA) {
+    __shared__ SolveSmem<W, R, NCB, B> sh;
+    const SolveArgs &A = FA.s;
+    const int64_t j = blockIdx.x;
+    const int t = threadIdx.x;
+    const int n = A.n;
+    const int M = n + (A.L + 1) * (A.L + 1);
+    const int64_t row = A.cidx ? (int64_t)A.cidx[j] : j;
+    SysIn in;
+    in.nx = A.nx; in.ny = A.ny; in.nz = A.nz; in.N = A.N;
+    in.S = A.S + row * n;
+    in.xe[0] = A.ex[j]; in.xe[1] = A.ey[j]; in.xe[2] = A.ez[j];
+    if (A.cx) {
+        in.ctr[0] = A.cx[row]; in.ctr[1] = A.cy[row]; in.ctr[2] = A.cz[row];
+    } else {
+        in.ctr[0] = in.xe[0]; in.ctr[1] = in.xe[1]; in.ctr[2] = in.xe[2];
+    }
+    in.s2 = A.s2[row];
+    in.n = n; in.L = A.L; in.k = A.k;
+    in.status = A.status; in.step = A.step;
+    FactorOut fo;
+    fo.F = FA.F + j * (int64_t)M * M;
+    fo.piv = FA.piv + j * M;
+    fo.rinv = FA.rinv + j * M;
+    fo.stepof = FA.stepof + j * M;
+    const bool ok = solve_system<W, R, NCB, B, false, 24, true>(sh, t, in, &fo);
+    if (t == 0) FA.fstat[j] = ok ? 0 : RBFSL_E_SINGULAR;
+}
+
+template <int W, int R, int NCB, int B, int WPE>
+hipError_t launch_factor_variant(const FactorArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL((k_factor<W, R, NCB, B, WPE>), dim3((unsigned)a.s.count), dim3(64 * W), 0, s, a);
+    return hipGetLastError();
 }
 
 template <int W, int R, int NCB, int B, int WPE>

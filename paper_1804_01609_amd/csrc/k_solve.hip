@@ -11,20 +11,28 @@ hipError_t solve_m96(const SolveArgs &a, hipStream_t s);
 hipError_t solve_m120(const SolveArgs &a, hipStream_t s);
 hipError_t solve_m128(const SolveArgs &a, hipStream_t s);
 hipError_t solve_m192(const SolveArgs &a, hipStream_t s);
+hipError_t factor_m48(const FactorArgs &a, hipStream_t s);
+hipError_t factor_m64(const FactorArgs &a, hipStream_t s);
+hipError_t factor_m81(const FactorArgs &a, hipStream_t s);
+hipError_t factor_m96(const FactorArgs &a, hipStream_t s);
+hipError_t factor_m120(const FactorArgs &a, hipStream_t s);
+hipError_t factor_m128(const FactorArgs &a, hipStream_t s);
+hipError_t factor_m192(const FactorArgs &a, hipStream_t s);
 
 struct Variant {
     int mcap;
     hipError_t (*fn)(const SolveArgs &, hipStream_t);
+    hipError_t (*factor)(const FactorArgs &, hipStream_t);
 };
 
 static const Variant kVariants[] = {
-    {48, solve_m48},
-    {64, solve_m64},
-    {81, solve_m81},
-    {96, solve_m96},
-    {120, solve_m120},
-    {128, solve_m128},
-    {192, solve_m192},
+    {48, solve_m48, factor_m48},
+    {64, solve_m64, factor_m64},
+    {81, solve_m81, factor_m81},
+    {96, solve_m96, factor_m96},
+    {120, solve_m120, factor_m120},
+    {128, solve_m128, factor_m128},
+    {192, solve_m192, factor_m192},
 };
 
 static const Variant *pick(int M) {
@@ -43,6 +51,13 @@ hipError_t launch_solve(const SolveArgs &a, hipStream_t s) {
     const Variant *v = pick(a.n + (a.L + 1) * (a.L + 1));
     if (!v) return hipErrorInvalidValue;
     return v->fn(a, s);
+}
+
+hipError_t launch_factor(const FactorArgs &a, hipStream_t s) {
+    if (a.s.count <= 0) return hipSuccess;
+    const Variant *v = pick(a.s.n + (a.s.L + 1) * (a.s.L + 1));
+    if (!v) return hipErrorInvalidValue;
+    return v->factor(a, s);
 }
 
 }  // namespace rbfsl

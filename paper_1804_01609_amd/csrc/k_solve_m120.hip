@@ -7,4 +7,7 @@ static_assert(variant_mcap<4, 2, 5, 6>() == 120, "capacity");
 hipError_t solve_m120(const SolveArgs &a, hipStream_t s) {
     return launch_solve_variant<4, 2, 5, 6, 3>(a, s);
 }
+hipError_t factor_m120(const FactorArgs &a, hipStream_t s) {
+    return launch_factor_variant<4, 2, 5, 6, 3>(a, s);
+}
 }  // namespace rbfsl

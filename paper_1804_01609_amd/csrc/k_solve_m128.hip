@@ -7,4 +7,7 @@ static_assert(variant_mcap<4, 2, 4, 8>() == 128, "capacity");
 hipError_t solve_m128(const SolveArgs &a, hipStream_t s) {
     return launch_solve_variant<4, 2, 4, 8, 3>(a, s);
 }
+hipError_t factor_m128(const FactorArgs &a, hipStream_t s) {
+    return launch_factor_variant<4, 2, 4, 8, 3>(a, s);
+}
 }  // namespace rbfsl

@@ -7,4 +7,7 @@ static_assert(variant_mcap<8, 3, 3, 8>() == 192, "capacity");
 hipError_t solve_m192(const SolveArgs &a, hipStream_t s) {
     return launch_solve_variant<8, 3, 3, 8, 2>(a, s);
 }
+hipError_t factor_m192(const FactorArgs &a, hipStream_t s) {
+    return launch_factor_variant<8, 3, 3, 8, 2>(a, s);
+}
 }  // namespace rbfsl

@@ -7,4 +7,7 @@ static_assert(variant_mcap<1, 1, 8, 8>() == 64, "capacity");
 hipError_t solve_m64(const SolveArgs &a, hipStream_t s) {
     return launch_solve_variant<1, 1, 8, 8, 3>(a, s);
 }
+hipError_t factor_m64(const FactorArgs &a, hipStream_t s) {
+    return launch_factor_variant<1, 1, 8, 8, 3>(a, s);
+}
 }  // namespace rbfsl

@@ -7,4 +7,7 @@ static_assert(variant_mcap<3, 2, 3, 9>() == 81, "capacity");
 hipError_t solve_m81(const SolveArgs &a, hipStream_t s) {
     return launch_solve_variant<3, 2, 3, 9, 3>(a, s);
 }
+hipError_t factor_m81(const FactorArgs &a, hipStream_t s) {
+    return launch_factor_variant<3, 2, 3, 9, 3>(a, s);
+}
 }  // namespace rbfsl

@@ -7,4 +7,7 @@ static_assert(variant_mcap<3, 2, 4, 8>() == 96, "capacity");
 hipError_t solve_m96(const SolveArgs &a, hipStream_t s) {
     return launch_solve_variant<3, 2, 4, 8, 3>(a, s);
 }
+hipError_t factor_m96(const FactorArgs &a, hipStream_t s) {
+    return launch_factor_variant<3, 2, 4, 8, 3>(a, s);
+}
 }  // namespace rbfsl

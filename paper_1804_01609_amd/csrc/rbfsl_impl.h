@@ -106,6 +106,41 @@ struct SolveArgs {
     int64_t step;
 };
 hipError_t launch_solve(const SolveArgs &a, hipStream_t s);
+
+// Factorizations of `count` systems (as SolveArgs describes them), stored
+// for reuse: system t's eliminated matrix (column-major M x M), pivot rows,
+// reciprocals and the step at which each row was pivoted; fstat[t] = 0 or
+// RBFSL_E_SINGULAR.
+struct FactorArgs {
+    SolveArgs s;
+    double *F;        // count x M x M
+    int32_t *piv;     // count x M
+    double *rinv;     // count x M
+    int32_t *stepof;  // count x M
+    int32_t *fstat;   // count
+};
+hipError_t launch_factor(const FactorArgs &a, hipStream_t s);
+
+// Weights from stored factorizations (the paper's centre-point stencils,
+// Section 3.3.2): for each evaluation point j, the system of centre node
+// cidx[j] (stencil S[cidx[j]], scale s2[cidx[j]]) with the right-hand side
+// [phi(|y_a - y_xi|); p(xi)] of xi_j, replayed through the stored
+// elimination and back substitution.  w: count x n.
+struct CachedArgs {
+    const double *nx, *ny, *nz;
+    int64_t N;
+    const double *ex, *ey, *ez;
+    const int32_t *S, *cidx;
+    const double *s2;
+    const double *F, *rinv;
+    const int32_t *piv, *stepof, *fstat;
+    int64_t count;
+    int n, L, k;
+    double *w;
+    int *status;
+    int64_t step;
+};
+hipError_t launch_solve_cached(const CachedArgs &a, hipStream_t s);
 int solve_variant_capacity(int M);  // capacity of the variant chosen for M (0: unsupported)
 
 hipError_t launch_apply(const double *w, const int32_t *S, const int32_t *cidx, int64_t N, int n,
