@@ -14,6 +14,8 @@ Sections (all by default):
              search pass and one persistent solve launch per kernel family
              and step, graph-replayed, autotuned), against the same runs
              stepped one after another on the plain path;
+  centre  -- the paper's centre-point stencils with every node's factorization
+             computed once and replayed each step (same C2 workload);
   served  -- a Poisson stream of transport requests (arrival rate 0.8 x the
              capacity calibrated on the request mix) through the pool's
              continuous-batching loop under a 200 GB HBM budget: p50/p99
@@ -110,7 +112,7 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--sections", default="plain,batched,served")
+    ap.add_argument("--sections", default="plain,centre,batched,served")
     ap.add_argument("--batched-steps", type=int, default=24)
     ap.add_argument("--served-requests", type=int, default=10)
     ap.add_argument("--served-step-scale", type=float, default=0.25,
@@ -192,6 +194,10 @@ def main():
     }
     say(f"plain: {value:.4g} interpolations/s, {ms_per_step:.3f} ms/step")
     sections = set(args.sections.split(","))
+    if "centre" in sections:
+        out["centre"] = bench_centre(cfg, X, q0, sync)
+        say(f"centre (cached factors): {out['centre']['value']:.4g} interpolations/s, "
+            f"{out['centre']['ms_per_step']:.3f} ms/step")
     if "batched" in sections:
         out["batched"] = bench_batched(args.batched_steps, sync)
         say(f"batched: {out['batched']['value']:.4g} interpolations/s "
@@ -202,6 +208,41 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, X, q0, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def bench_centre(cfg, X, q0, sync, steps=100):
+    """C2 with the paper's centre-point stencils (Section 3.3.2) and cached
+    factorizations: one factorization per node at create, then per step the
+    search for the nearest node, the right-hand side and the stored
+    elimination replayed (HBM-bound: 8 M^2 bytes per point)."""
+    N, n, L, k = cfg["N"], cfg["n"], cfg["L"], cfg["k"]
+    M = n + (L + 1) ** 2
+    p = rb.make_params(n, L, k, 1, cfg["vel_id"], cfg["vp"], cfg["dt"], 0.0, cfg["ntr"], cache_factors=1)
+    sync()
+    t = time.perf_counter()
+    tr = rb.Transport(X, p)
+    sync()
+    create_s = time.perf_counter() - t
+    tr.set_q(q0)
+    tr.run(2)
+    tr.profile(True)
+    sync()
+    t = time.perf_counter()
+    tr.run(steps)
+    sync()
+    dt = time.perf_counter() - t
+    ph, nrec = tr.phase_times()
+    tr.close()
+    solve_ms = ph[2] / max(nrec, 1)
+    bytes_solve = 8.0 * M * M * N
+    return {"workload": cfg["name"] + "-centre-point-stencils-cached-factors", "steps": steps,
+            "value": N * steps / dt, "unit": "interpolations/s", "ms_per_step": 1e3 * dt / steps,
+            "create_s_incl_factorization": create_s, "factor_bytes": 8 * M * M * N,
+            "phase_ms_per_step": {nm: ph[i] / max(nrec, 1) for i, nm in enumerate(["trace", "knn", "solve", "apply"])},
+            "roofline_solve": {"kernel": "k_solve_cached", "bound": "hbm",
+                               "achieved": bytes_solve / (solve_ms * 1e-3) / 1e9, "peak": 8000.0,
+                               "unit": "GB/s", "frac": bytes_solve / (solve_ms * 1e-3) / 8e12,
+                               "algorithmic_bytes_per_launch": bytes_solve}}
 
 
 def _run_inputs(r):

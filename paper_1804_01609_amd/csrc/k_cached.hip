@@ -11,9 +11,11 @@
 // unknown, z_k = y_pk r_k, y_i = fma(-u_ik, z_k, y_i) for rows pivoted before
 // step k.  The weights are therefore bit for bit those of refactoring.
 //
-// One wave per evaluation point, rows on lanes (R row slots); the stored
-// matrix streams from HBM column by column (read twice), so the kernel is
-// bound by HBM bandwidth: 16 M^2 bytes per point.
+// One wave per evaluation point, positions in pivot order on lanes (R slots):
+// the stored matrix keeps its rows in pivot order, so step k's multipliers
+// are the positions below k of column k and its U entries the positions above
+// it; each stored element is read once, and the kernel is bound by HBM
+// bandwidth: 8 M^2 bytes per point.
 #include "dev_util.h"
 #include "k_solve.h"
 
@@ -48,10 +50,9 @@ __global__ void __launch_bounds__(64) k_solve_cached(CachedArgs A) {
     if (lane == 0) basis_all(L, al, be, u, peb);
     wave_lds_sync();
 
-    // right-hand side, as the assembly builds it
+    // right-hand side, as the assembly builds it, moved to pivot order
+    __shared__ double yl[192];
     const int32_t *Srow = A.S + K * n;
-    double y[R];
-    int stp[R];
     const int32_t *stepof = A.stepof + K * M;
     sfor<0, R>([&](auto RI) SI {
         constexpr int r = RI;
@@ -72,55 +73,105 @@ __global__ void __launch_bounds__(64) k_solve_cached(CachedArgs A) {
         } else if (i < M) {
             rhs = peb[i - n];
         }
-        y[r] = rhs;
-        stp[r] = (i < M) ? stepof[i] : -1;  // padding rows count as pivoted from the start
+        if (i < M) yl[stepof[i]] = rhs;
+    });
+    wave_lds_sync();
+    double y[R];  // y at position q = lane + 64 r (the row pivoted at step q)
+    sfor<0, R>([&](auto RI) SI {
+        constexpr int r = RI;
+        const int q = lane + 64 * r;
+        y[r] = (q < M) ? yl[q] : 0.0;
     });
 
     const double *F = A.F + K * (int64_t)M * M;
-    const int32_t *piv = A.piv + K * M;
     const double *rinv = A.rinv + K * M;
-    // forward: the elimination's updates of the right-hand side
-    for (int kk = 0; kk < M; ++kk) {
-        const int p = __builtin_amdgcn_readfirstlane(piv[kk]);
-        const double rk = rinv[kk];
-        const int pl = p & 63, pr = p >> 6;
-        double yp = bcast_d(y[0], pl);
-        sfor<1, R>([&](auto RI) SI {
-            constexpr int r = RI;
-            const double yr = bcast_d(y[r], pl);
-            yp = (pr == r) ? yr : yp;
+    // Columns are fetched CK steps ahead into registers (double buffered), so
+    // the loads of a whole block are in flight while the previous block runs.
+    constexpr int CK = 8;
+    double cb[CK][R], nb[CK][R];
+    // forward: the elimination's updates of the right-hand side; positions
+    // at or before k are pivoted rows (multiplier 0)
+    auto fetch_fwd = [&](double (&buf)[CK][R], int k0) SI {
+        sfor<0, CK>([&](auto CI) SI {
+            constexpr int c = CI;
+            const int kk = k0 + c;
+            sfor<0, R>([&](auto RI) SI {
+                constexpr int r = RI;
+                const int q = lane + 64 * r;
+                double v = 0.0;
+                if (q > kk && q < M) v = F[(int64_t)kk * M + q];
+                buf[c][r] = v;
+            });
         });
-        sfor<0, R>([&](auto RI) SI {
-            constexpr int r = RI;
-            const int i = lane + 64 * r;
-            const double a = (i < M) ? F[(int64_t)kk * M + i] : 0.0;
-            const double l = (stp[r] <= kk) ? 0.0 : a * rk;
-            y[r] = fma(-l, yp, y[r]);
+    };
+    fetch_fwd(nb, 0);
+    for (int k0 = 0; k0 < M; k0 += CK) {
+        sfor<0, CK>([&](auto CI) SI { sfor<0, R>([&](auto RI) SI { cb[CI][RI] = nb[CI][RI]; }); });
+        if (k0 + CK < M) fetch_fwd(nb, k0 + CK);
+        sfor<0, CK>([&](auto CI) SI {
+            constexpr int c = CI;
+            const int kk = k0 + c;
+            if (kk < M) {
+                const double rk = rinv[kk];
+                const int pl = kk & 63, pr = kk >> 6;
+                double yp = bcast_d(y[0], pl);
+                sfor<1, R>([&](auto RI) SI {
+                    constexpr int r = RI;
+                    const double yr = bcast_d(y[r], pl);
+                    yp = (pr == r) ? yr : yp;
+                });
+                sfor<0, R>([&](auto RI) SI {
+                    constexpr int r = RI;
+                    const int q = lane + 64 * r;
+                    const double l = (q <= kk) ? 0.0 : cb[c][r] * rk;
+                    y[r] = fma(-l, yp, y[r]);
+                });
+            }
         });
     }
     // back substitution; z_k for k < n are the weights
     bool bad = false;
-    for (int kk = M - 1; kk >= 0; --kk) {
-        const int p = __builtin_amdgcn_readfirstlane(piv[kk]);
-        const double rk = rinv[kk];
-        const int pl = p & 63, pr = p >> 6;
-        double yk = bcast_d(y[0], pl);
-        sfor<1, R>([&](auto RI) SI {
-            constexpr int r = RI;
-            const double yr = bcast_d(y[r], pl);
-            yk = (pr == r) ? yr : yk;
+    auto fetch_bwd = [&](double (&buf)[CK][R], int k1) SI {  // steps k1, k1-1, ...
+        sfor<0, CK>([&](auto CI) SI {
+            constexpr int c = CI;
+            const int kk = k1 - c;
+            sfor<0, R>([&](auto RI) SI {
+                constexpr int r = RI;
+                const int q = lane + 64 * r;
+                double v = 0.0;
+                if (q < kk) v = F[(int64_t)kk * M + q];
+                buf[c][r] = v;
+            });
         });
-        const double zk = yk * rk;
-        if (kk < n) {
-            if (lane == 0) A.w[j * n + kk] = zk;
-            if (!isfinite(zk)) bad = true;
-        }
-        sfor<0, R>([&](auto RI) SI {
-            constexpr int r = RI;
-            const int i = lane + 64 * r;
-            const double uik = (i < M) ? F[(int64_t)kk * M + i] : 0.0;
-            const double yn = fma(-uik, zk, y[r]);
-            y[r] = (stp[r] < kk) ? yn : y[r];
+    };
+    fetch_bwd(nb, M - 1);
+    for (int k1 = M - 1; k1 >= 0; k1 -= CK) {
+        sfor<0, CK>([&](auto CI) SI { sfor<0, R>([&](auto RI) SI { cb[CI][RI] = nb[CI][RI]; }); });
+        if (k1 - CK >= 0) fetch_bwd(nb, k1 - CK);
+        sfor<0, CK>([&](auto CI) SI {
+            constexpr int c = CI;
+            const int kk = k1 - c;
+            if (kk >= 0) {
+                const double rk = rinv[kk];
+                const int pl = kk & 63, pr = kk >> 6;
+                double yk = bcast_d(y[0], pl);
+                sfor<1, R>([&](auto RI) SI {
+                    constexpr int r = RI;
+                    const double yr = bcast_d(y[r], pl);
+                    yk = (pr == r) ? yr : yk;
+                });
+                const double zk = yk * rk;
+                if (kk < n) {
+                    if (lane == 0) A.w[j * n + kk] = zk;
+                    if (!isfinite(zk)) bad = true;
+                }
+                sfor<0, R>([&](auto RI) SI {
+                    constexpr int r = RI;
+                    const int q = lane + 64 * r;
+                    const double yn = fma(-cb[c][r], zk, y[r]);
+                    y[r] = (q < kk) ? yn : y[r];
+                });
+            }
         });
     }
     if (bad && lane == 0) {

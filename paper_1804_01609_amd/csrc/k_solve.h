@@ -88,9 +88,10 @@ struct SysIn {
 };
 
 // Where a factorization goes (factor-only mode): the eliminated matrix,
-// column-major M x M (rows not yet pivoted at step k hold, in column k, the
-// value that step divided by the pivot; the others hold U), the pivot row
-// and reciprocal of every step, and the step at which every row was pivoted.
+// column-major M x M with the rows in pivot order (row i at position
+// stepof[i]), so that column k holds below position k the values step k
+// divided by the pivot and above it U; the pivot row and reciprocal of every
+// step, and the step at which every row was pivoted.
 struct FactorOut {
     double *F;
     int32_t *piv;
@@ -443,7 +444,7 @@ __device__ __forceinline__ bool solve_system(SolveSmem<W, R, NCB, B, CM> &sh, co
                 sfor<0, R>([&](auto RI) SI {
                     constexpr int r = RI;
                     const int i = lane + 64 * r;
-                    if (i < M) fo->F[(int64_t)jc * M + i] = a[r][sl];
+                    if (i < M) fo->F[(int64_t)jc * M + stepof[r]] = a[r][sl];
                 });
             }
         });
