@@ -388,8 +388,8 @@ class Pool:
         return a.value, b.value, c.value
 
     def get_q(self, rid, out=None):
-        if out is None:
-            out = np.zeros(self._shape[rid])
+        if out is None:  # an unknown id is the library's to reject
+            out = np.zeros(self._shape.get(rid, (1,)))
         ptr, dev, keep = _ptr(out, np.float64)
         self._chk(lib().rbfsl_pool_get_q(self._p, int(rid), ptr, dev))
         return out
