@@ -70,6 +70,16 @@ def lib():
         L.orc_run.argtypes = [ctypes.c_int64, _D, ctypes.POINTER(Params), ctypes.c_int64,
                               ctypes.c_int64, _D, _I64]
         L.orc_run.restype = ctypes.c_int
+        L.orc_bspline.argtypes = [ctypes.c_double]
+        L.orc_bspline.restype = ctypes.c_double
+        L.orc_patch_coef.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _D, _D, ctypes.c_double, _D, _D]
+        L.orc_patch_coef.restype = ctypes.c_int
+        L.orc_patch_eval.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _D, _D, ctypes.c_double, _D, _D]
+        L.orc_patch_eval.restype = ctypes.c_double
+        L.orc_pu_patches.argtypes = [ctypes.c_int64, _D, ctypes.c_int64, _D, ctypes.c_double, _I64, _I32]
+        L.orc_pu_step.argtypes = [ctypes.c_int64, _D, ctypes.c_int64, _D, ctypes.c_double, _I64, _I32,
+                                  ctypes.POINTER(Params), ctypes.c_int64, ctypes.c_int64, _I64, _D, _D, _D, _I32]
+        L.orc_pu_step.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -180,3 +190,86 @@ def run(nodes, params, q0, nsteps, m0=0):
     fs = ctypes.c_int64(-1)
     st = lib().orc_run(N, _d(nodes), ctypes.byref(params), int(m0), int(nsteps), _d(q), ctypes.byref(fs))
     return q, st, fs.value
+
+
+# ---------------------------------------------------------------- RBF-PU
+
+
+def bspline(r):
+    """The cubic B-spline weight function (eq. bspline)."""
+    return lib().orc_bspline(float(r))
+
+
+def pu_radius(n, N):
+    """One patch radius for every patch, R = 2 sqrt(n/N) (eq. rad_patches)."""
+    return 2.0 * np.sqrt(n / N)
+
+
+def pu_count(a, n, N):
+    """Number of patches, ceil(a N / n) (eq. num_patches)."""
+    return int(np.ceil(a * N / n))
+
+
+def pu_patches(nodes, centers, R):
+    """Patch membership: (counts, offsets, idx) with the nodes of patch l in
+    idx[offsets[l]:offsets[l+1]], in (d^2, index) order."""
+    nodes, centers = _f64(nodes), _f64(centers)
+    Mp = centers.shape[0]
+    counts = np.zeros(Mp, dtype=np.int64)
+    lib().orc_pu_patches(nodes.shape[0], _d(nodes), Mp, _d(centers), float(R),
+                         counts.ctypes.data_as(_I64), None)
+    idx = np.zeros(max(int(counts.sum()), 1), dtype=np.int32)
+    lib().orc_pu_patches(nodes.shape[0], _d(nodes), Mp, _d(centers), float(R),
+                         counts.ctypes.data_as(_I64), idx.ctypes.data_as(_I32))
+    offsets = np.concatenate([[0], np.cumsum(counts)])
+    return counts, offsets, idx
+
+
+def patch_coef(L, k, xs, omega, R2, qv):
+    xs = _f64(xs).reshape(-1, 3)
+    n = xs.shape[0]
+    coef = np.zeros(n + (L + 1) ** 2)
+    st = lib().orc_patch_coef(n, L, k, _d(xs), _d(_f64(omega)), float(R2), _d(_f64(qv)), _d(coef))
+    return coef, st
+
+
+def patch_eval(L, k, xs, omega, R2, coef, x):
+    xs = _f64(xs).reshape(-1, 3)
+    return lib().orc_patch_eval(xs.shape[0], L, k, _d(xs), _d(_f64(omega)), float(R2), _d(_f64(coef)),
+                                _d(_f64(x)))
+
+
+def pu_step(nodes, centers, R, patches, params, m, jl, q_in):
+    """One RBF-PU step for the target nodes jl; patches from pu_patches.
+    Returns dict(xi, q, status)."""
+    nodes, centers = _f64(nodes), _f64(centers)
+    N = nodes.shape[0]
+    counts, _, idx = patches
+    counts = np.ascontiguousarray(counts, dtype=np.int64)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    jl = np.ascontiguousarray(jl, dtype=np.int64)
+    J = jl.shape[0]
+    q_in = _f64(q_in).reshape(params.ntr, N)
+    xi = np.zeros((J, 3))
+    qo = np.zeros((params.ntr, J))
+    st = np.zeros(J, dtype=np.int32)
+    lib().orc_pu_step(N, _d(nodes), centers.shape[0], _d(centers), float(R), counts.ctypes.data_as(_I64),
+                      idx.ctypes.data_as(_I32), ctypes.byref(params), int(m), J, jl.ctypes.data_as(_I64),
+                      _d(q_in), _d(xi), _d(qo), st.ctypes.data_as(_I32))
+    return dict(xi=xi, q=qo, status=st)
+
+
+def pu_run(nodes, centers, R, params, q0, nsteps, m0=0):
+    """Full RBF-PU run; returns (q, status, fail_step)."""
+    nodes = _f64(nodes)
+    N = nodes.shape[0]
+    patches = pu_patches(nodes, centers, R)
+    q = _f64(q0).reshape(params.ntr, N).copy()
+    jl = np.arange(N, dtype=np.int64)
+    for m in range(m0, m0 + nsteps):
+        o = pu_step(nodes, centers, R, patches, params, m, jl, q)
+        bad = np.flatnonzero(o["status"])
+        if bad.size:
+            return q, int(o["status"][bad[0]]), m
+        q = o["q"]
+    return q, ORC_OK, -1

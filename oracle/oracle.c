@@ -21,6 +21,10 @@
  *   4. that system solved by Gaussian elimination with partial pivoting (the
  *      LU route of Section 3.3.2);
  *   5. q^{m+1}_j = s(xi_j), evaluated in cardinal form as sum_a w_a q_a.
+ * and, as the second interpolation method of Section 3.3, the RBF-PU step:
+ * the augmented interpolants of the patches (spherical caps) solved for the
+ * right-hand side [q; 0] and blended with the B-spline partition of unity
+ * at every departure point (the functions orc_bspline ... orc_pu_step).
  *
  * Readings of points the paper leaves open (all listed in the design notes):
  *   - the basis of the degree-L harmonic space is the graded local basis
@@ -597,4 +601,207 @@ int orc_run(int64_t N, const double *nodes, const orc_params *p, int64_t m0, int
     }
     free(jl); free(qn); free(st);
     return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* RBF-PU interpolation (Section 2.3: patches, the weight functions          */
+/* eq. wght_func with the cubic B-spline eq. bspline, the PU weights         */
+/* eq. pu_func and the interpolant eq. PU_interp) in the SL step             */
+/* (Section 3.3.3: one radius R = 2 sqrt(n/N), eq. rad_patches, and          */
+/* ceil(aN/n) patches, eq. num_patches).                                     */
+/* Readings: the patch centres are an input (a quasi-uniform point set);     */
+/* patch l holds every node with |x - omega_l|^2 < R^2, in (d^2, index)      */
+/* order; its interpolant is eq. rbf_poly in the frame centred on omega_l    */
+/* with squared scale R^2; the patches containing a point are taken in       */
+/* (d^2, l) order, and s(x) = (sum_l phi_l s_l(x)) / (sum_l phi_l) with the  */
+/* numerator (fma) and the denominator (add) accumulated in that order;      */
+/* phi_l = B(|x - omega_l| / R), the distance as sqrt(d^2).                  */
+/* ------------------------------------------------------------------------ */
+
+/* the cubic B-spline of eq. bspline */
+double orc_bspline(double r) {
+    if (r < 0.5) {
+        double v = 4.0 * (r - 1.0);
+        v = v * r;
+        v = v * r;
+        return (2.0 / 3.0) + v;
+    }
+    if (r < 1.0) {
+        double t = r - 1.0;
+        double v = t * t;
+        v = v * t;
+        return (-4.0 / 3.0) * v;
+    }
+    return 0.0;
+}
+
+/* nodes of one patch: returns how many x_i have |x_i - omega|^2 < R2 and
+ * writes the first min(count, cap) of them, in (d^2, i) order, to idx */
+int64_t orc_patch_nodes(int64_t N, const double *nodes, const double *omega, double R2, int64_t cap,
+                        int32_t *idx) {
+    key_t_ *keys = (key_t_ *)malloc(sizeof(key_t_) * (size_t)N);
+    for (int64_t i = 0; i < N; ++i) {
+        keys[i].d2 = dist2(nodes + 3 * i, omega);
+        keys[i].i = (int32_t)i;
+    }
+    qsort(keys, (size_t)N, sizeof(key_t_), key_cmp);
+    int64_t cnt = 0;
+    while (cnt < N && keys[cnt].d2 < R2) {
+        if (cnt < cap) idx[cnt] = keys[cnt].i;
+        ++cnt;
+    }
+    free(keys);
+    return cnt;
+}
+
+/* coefficients [c; d] of one patch's interpolant (eq. rbf_poly): the system
+ * eq. rbf_poly_linsys of its nodes xs (n x 3) solved for [qv; 0] */
+int orc_patch_coef(int n, int L, int k, const double *xs, const double *omega, double R2,
+                   const double *qv, double *coef) {
+    int mL = (L + 1) * (L + 1);
+    int M = n + mL;
+    double *A = (double *)malloc(sizeof(double) * (size_t)M * (size_t)M);
+    double *r = (double *)malloc(sizeof(double) * (size_t)M);
+    orc_assemble(n, L, k, xs, omega, R2, omega, A, r);  /* the right-hand side is replaced */
+    for (int a = 0; a < n; ++a) r[a] = qv[a];
+    for (int q = 0; q < mL; ++q) r[n + q] = 0.0;
+    int st = orc_gauss_solve(M, A, r);
+    memcpy(coef, r, sizeof(double) * (size_t)M);
+    free(A);
+    free(r);
+    return st;
+}
+
+/* one patch's interpolant at x: sum_b c_b phi(|y_b - y_x|) + sum_q d_q p_q(x),
+ * one fma chain in that order, in the patch's local coordinates */
+double orc_patch_eval(int n, int L, int k, const double *xs, const double *omega, double R2,
+                      const double *coef, const double *x) {
+    int mL = (L + 1) * (L + 1);
+    double s = (R2 > 0.0) ? sqrt(R2) : 1.0;
+    double inv_s = 1.0 / s;
+    double e1[3], e2[3];
+    frame(omega, e1, e2);
+    double yx[3], alx, bex, ux;
+    local_coords(x, omega, e1, e2, inv_s, yx, &alx, &bex, &ux);
+    double acc = 0.0;
+    for (int b = 0; b < n; ++b) {
+        double yb[3], al, be, u;
+        local_coords(xs + 3 * b, omega, e1, e2, inv_s, yb, &al, &be, &u);
+        double d0 = yb[0] - yx[0], d1 = yb[1] - yx[1], d2 = yb[2] - yx[2];
+        acc = fma(coef[b], phs((d0 * d0 + d1 * d1) + d2 * d2, k), acc);
+    }
+    double *px = (double *)malloc(sizeof(double) * (size_t)mL);
+    basis(L, alx, bex, ux, px);
+    for (int q = 0; q < mL; ++q) acc = fma(coef[n + q], px[q], acc);
+    free(px);
+    return acc;
+}
+
+/* patch membership of all Mp patches: counts (Mp) and, when idx is given,
+ * the concatenated node lists (offsets from the running sum of counts) */
+void orc_pu_patches(int64_t N, const double *nodes, int64_t Mp, const double *centers, double R,
+                    int64_t *counts, int32_t *idx) {
+    const double R2 = R * R;
+    int64_t *off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(Mp + 1));
+    if (idx) {
+        off[0] = 0;
+        for (int64_t l = 0; l < Mp; ++l) off[l + 1] = off[l] + counts[l];
+    }
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t l = 0; l < Mp; ++l) {
+        if (idx)
+            orc_patch_nodes(N, nodes, centers + 3 * l, R2, counts[l], idx + off[l]);
+        else
+            counts[l] = orc_patch_nodes(N, nodes, centers + 3 * l, R2, 0, NULL);
+    }
+    free(off);
+}
+
+/* One RBF-PU SL step m for the J target nodes jl (Algorithm 1 with the
+ * interpolant eq. PU_interp).  p gives L, k, the flow, the integrator, dt,
+ * t0 and the tracer count; the patches are given by counts/idx (from
+ * orc_pu_patches).  q_in: ntr x N; outputs (may be NULL): xi (J x 3), q_out
+ * (ntr x J), st_out (J: ORC_OK, ORC_SINGULAR for a singular patch system
+ * used at the point, ORC_INVAL for a point in no patch).  Returns the number
+ * of failing points. */
+int orc_pu_step(int64_t N, const double *nodes, int64_t Mp, const double *centers, double R,
+                const int64_t *counts, const int32_t *idx, const orc_params *p, int64_t m,
+                int64_t J, const int64_t *jl, const double *q_in, double *xi_out, double *q_out,
+                int32_t *st_out) {
+    const int L = p->L, k = p->k, ntr = p->ntr;
+    const int mL = (L + 1) * (L + 1);
+    const double R2 = R * R;
+    int64_t *off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(Mp + 1));
+    int64_t *coff = (int64_t *)malloc(sizeof(int64_t) * (size_t)(Mp + 1));
+    off[0] = 0;
+    coff[0] = 0;
+    for (int64_t l = 0; l < Mp; ++l) {
+        off[l + 1] = off[l] + counts[l];
+        coff[l + 1] = coff[l] + (counts[l] + mL) * ntr;
+    }
+    double *coef = (double *)malloc(sizeof(double) * (size_t)coff[Mp]);
+    int *pst = (int *)malloc(sizeof(int) * (size_t)Mp);
+    /* the patches' interpolants of every tracer */
+#pragma omp parallel for schedule(dynamic, 2)
+    for (int64_t l = 0; l < Mp; ++l) {
+        const int n = (int)counts[l];
+        double *xs = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+        double *qv = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+        for (int a = 0; a < n; ++a)
+            for (int i = 0; i < 3; ++i) xs[3 * a + i] = nodes[3 * (int64_t)idx[off[l] + a] + i];
+        pst[l] = ORC_OK;
+        for (int t = 0; t < ntr && pst[l] == ORC_OK; ++t) {
+            for (int a = 0; a < n; ++a) qv[a] = q_in[(int64_t)t * N + idx[off[l] + a]];
+            pst[l] = orc_patch_coef(n, L, k, xs, centers + 3 * l, R2, qv, coef + coff[l] + (int64_t)t * (n + mL));
+        }
+        free(xs);
+        free(qv);
+    }
+    step_coefs sc;
+    step_coefs_at(p->vel_id, p->vp, p->rk, p->t0, p->dt, m, &sc);
+    int bad = 0;
+#pragma omp parallel reduction(+ : bad)
+    {
+        key_t_ *keys = (key_t_ *)malloc(sizeof(key_t_) * (size_t)Mp);
+        double *num = (double *)malloc(sizeof(double) * (size_t)ntr);
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t t = 0; t < J; ++t) {
+            double xi[3];
+            departure(p->vel_id, &sc, p->dt, nodes + 3 * jl[t], xi);
+            for (int64_t l = 0; l < Mp; ++l) {
+                keys[l].d2 = dist2(centers + 3 * l, xi);
+                keys[l].i = (int32_t)l;
+            }
+            qsort(keys, (size_t)Mp, sizeof(key_t_), key_cmp);
+            int st = ORC_OK;
+            double den = 0.0;
+            for (int r = 0; r < ntr; ++r) num[r] = 0.0;
+            for (int64_t c = 0; c < Mp && keys[c].d2 < R2; ++c) {
+                const int64_t l = keys[c].i;
+                if (pst[l] != ORC_OK) { st = pst[l]; continue; }
+                const int n = (int)counts[l];
+                double *xs = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+                for (int a = 0; a < n; ++a)
+                    for (int i = 0; i < 3; ++i) xs[3 * a + i] = nodes[3 * (int64_t)idx[off[l] + a] + i];
+                const double phi = orc_bspline(sqrt(keys[c].d2) / R);
+                for (int r = 0; r < ntr; ++r) {
+                    const double sv = orc_patch_eval(n, L, k, xs, centers + 3 * l, R2,
+                                                     coef + coff[l] + (int64_t)r * (n + mL), xi);
+                    num[r] = fma(phi, sv, num[r]);
+                }
+                den = den + phi;
+                free(xs);
+            }
+            if (st == ORC_OK && !(den > 0.0)) st = ORC_INVAL;
+            if (st != ORC_OK) bad += 1;
+            if (st_out) st_out[t] = st;
+            if (xi_out) memcpy(xi_out + 3 * t, xi, sizeof(xi));
+            if (q_out)
+                for (int r = 0; r < ntr; ++r) q_out[(int64_t)r * J + t] = num[r] / den;
+        }
+        free(keys);
+        free(num);
+    }
+    free(off); free(coff); free(coef); free(pst);
+    return bad;
 }
