@@ -81,7 +81,9 @@ typedef struct {
     int32_t k;            /* PHS order, phi = r^(2k+1), 0 <= k <= L; -1 selects k = L      */
     int32_t stencil_mode; /* 0: n nearest nodes of xi_j, centred at xi_j;
                              1: the paper's centre-point stencils: the n nearest nodes
-                                of the node nearest to xi_j (Section 3.3.2)            */
+                                of the node nearest to xi_j (Section 3.3.2);
+                             RBFSL_STENCIL_PU (2): RBF-PU, rbfsl_create_pu only; n is
+                                the nominal number of nodes per patch                 */
     int32_t velocity_id;  /* RBFSL_VEL_*                                                  */
     int32_t n_tracers;    /* number of fields sharing each step's weights, >= 1           */
     int32_t integrator;   /* RBFSL_RK4 (0) or RBFSL_RK5_FEHLBERG (1)                      */
@@ -101,6 +103,35 @@ typedef struct {
  * On failure *out is NULL. */
 int rbfsl_create(const double *nodes_xyz, int64_t N, int nodes_on_device,
                  const rbfsl_params *p, void *hip_stream, rbfsl_ctx **out);
+
+/* RBF-PU interpolation (Sections 2.3 and 3.3.3) in place of the local
+ * stencils.  Patch l is the spherical cap |x - c_l| < R around
+ * centers_xyz[l] (Mp x 3, copied; the paper's choice: a quasi-uniform set of
+ * ceil(a N / n) points and R = 2 sqrt(n/N), eq. rad_patches and
+ * eq. num_patches); its nodes are every node inside it, in ascending
+ * (distance^2, index) order.  Each patch's augmented interpolant (eq. rbf_poly
+ * in the patch's frame, squared scale R * R) is factored once here; a step
+ * solves it for the tracer values at the patch's nodes and evaluates, at each
+ * departure point, the blend (eq. PU_interp) of the interpolants of the
+ * patches containing it (ascending (distance^2, patch index)) with the cubic
+ * B-spline weights phi_l = B(|xi - c_l| / R) (eq. bspline, eq. pu_func):
+ * q = (sum_l phi_l s_l(xi)) / (sum_l phi_l).
+ * p->stencil_mode must be RBFSL_STENCIL_PU and cache_factors 0; 0 < R <= 2.
+ * Fails with RBFSL_E_SEARCH when a patch is empty, holds more nodes than a
+ * system of rbfsl_max_system() unknowns allows, or more than its node list
+ * (about 2n + 64 nodes); a step fails with RBFSL_E_SEARCH when a departure
+ * point lies in no patch or in more than 16, and with RBFSL_E_SINGULAR when a
+ * patch it uses has a singular system.  rbfsl_debug_stencils and
+ * rbfsl_debug_weights do not apply (RBFSL_E_INVAL). */
+enum { RBFSL_STENCIL_PU = 2 };
+int rbfsl_create_pu(const double *nodes_xyz, int64_t N, int nodes_on_device, const double *centers_xyz,
+                    int64_t Mp, double R, const rbfsl_params *p, void *hip_stream, rbfsl_ctx **out);
+/* Patch geometry of an RBF-PU context: patch count, node-list capacity ncap,
+ * largest patch (any output may be NULL).  RBFSL_E_INVAL for other contexts. */
+int rbfsl_pu_info(const rbfsl_ctx *ctx, int64_t *npatch, int32_t *ncap, int32_t *nmax, double *R);
+/* Parity tap: every patch's node count (Mp) and node list (Mp x ncap, the
+ * first count entries of each row are the patch's nodes). */
+int rbfsl_debug_patches(rbfsl_ctx *ctx, int32_t *counts, int32_t *idx);
 
 /* Set q^m (n_tracers x N row-major, copied).  Does not change the step index. */
 int rbfsl_set_q(rbfsl_ctx *ctx, const double *q, int on_device);

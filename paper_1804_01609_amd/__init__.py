@@ -25,13 +25,14 @@ RBFSL_E_SEARCH = -7
 RBFSL_E_BUDGET = -8
 
 VEL_ZERO, VEL_SOLID_BODY, VEL_DEFORM, VEL_NL2010 = 0, 1, 2, 3
+STENCIL_PU = 2  # RBF-PU (PuTransport)
 RK4, RK5_FEHLBERG = 0, 1
 
 EXPORTS = [
     "rbfsl_create", "rbfsl_set_q", "rbfsl_step", "rbfsl_run", "rbfsl_get_q", "rbfsl_get_state",
     "rbfsl_get_failures", "rbfsl_profile", "rbfsl_phase_times", "rbfsl_debug_departure", "rbfsl_debug_stencils", "rbfsl_debug_weights",
     "rbfsl_knn", "rbfsl_weights", "rbfsl_max_system", "rbfsl_strerror", "rbfsl_last_error",
-    "rbfsl_destroy",
+    "rbfsl_destroy", "rbfsl_create_pu", "rbfsl_pu_info", "rbfsl_debug_patches",
     "rbfsl_pool_create", "rbfsl_pool_run_bytes", "rbfsl_pool_add", "rbfsl_pool_step", "rbfsl_pool_run_info",
     "rbfsl_pool_get_q", "rbfsl_pool_remove", "rbfsl_pool_info", "rbfsl_pool_variants", "rbfsl_pool_set_variant",
     "rbfsl_pool_tune", "rbfsl_pool_serve", "rbfsl_pool_last_error", "rbfsl_pool_destroy",
@@ -106,6 +107,11 @@ def lib():
         L.rbfsl_debug_departure.argtypes = [_P, _P]
         L.rbfsl_debug_stencils.argtypes = [_P, _P]
         L.rbfsl_debug_weights.argtypes = [_P, _P]
+        L.rbfsl_create_pu.argtypes = [_P, i64, ctypes.c_int, _P, i64, ctypes.c_double, ctypes.POINTER(Params), _P,
+                                      ctypes.POINTER(_P)]
+        L.rbfsl_pu_info.argtypes = [_P, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                    ctypes.POINTER(ctypes.c_double)]
+        L.rbfsl_debug_patches.argtypes = [_P, _P, _P]
         L.rbfsl_knn.argtypes = [_P, i64, _P, i64, i32, _P, _P, ctypes.c_int, _P]
         L.rbfsl_weights.argtypes = [_P, i64, _P, _P, _P, _P, i64, i32, i32, i32, _P, _P, ctypes.c_int, _P]
         L.rbfsl_max_system.restype = ctypes.c_int
@@ -285,6 +291,55 @@ class Transport:
         w = np.zeros((self.N, self.params.n))
         _check(lib().rbfsl_debug_weights(self._ctx, w.ctypes.data_as(_P)), self._ctx)
         return w
+
+
+class PuTransport(Transport):
+    """RBF-PU transport (Sections 2.3 and 3.3.3): patches are the caps of
+    radius R around `centers` (Mp x 3); by default the paper's choices,
+    R = 2 sqrt(n/N) and ceil(a N / n) quasi-uniform centres, come from
+    `pu_radius` / `pu_count` and the caller's point set.  params.stencil_mode
+    must be STENCIL_PU."""
+
+    def __init__(self, nodes, centers, R, params, stream=None):
+        L = lib()
+        ptr, dev, keep = _ptr(nodes, np.float64)
+        cptr, cdev, ckeep = _ptr(centers, np.float64)
+        if cdev != dev:
+            raise ValueError("nodes and centers must both be host arrays or both device tensors")
+        self.N = int(nodes.shape[0])
+        self.params = params
+        self.ntr = params.n_tracers
+        s = ctypes.c_void_p(stream) if stream is not None else _stream(dev)
+        self._ctx = _P()
+        code = L.rbfsl_create_pu(ptr, self.N, dev, cptr, int(centers.shape[0]), float(R), ctypes.byref(params), s,
+                                 ctypes.byref(self._ctx))
+        if code != RBFSL_OK:
+            self._ctx = None
+            _check(code)
+
+    def info(self):
+        Mp, ncap, nmax, R = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _check(lib().rbfsl_pu_info(self._ctx, ctypes.byref(Mp), ctypes.byref(ncap), ctypes.byref(nmax),
+                                   ctypes.byref(R)), self._ctx)
+        return dict(patches=Mp.value, ncap=ncap.value, nmax=nmax.value, R=R.value)
+
+    def patches(self):
+        """(counts, list of node-index arrays) of every patch."""
+        inf = self.info()
+        counts = np.zeros(inf["patches"], dtype=np.int32)
+        idx = np.zeros((inf["patches"], inf["ncap"]), dtype=np.int32)
+        _check(lib().rbfsl_debug_patches(self._ctx, counts.ctypes.data_as(_P), idx.ctypes.data_as(_P)), self._ctx)
+        return counts, [idx[l, :counts[l]] for l in range(counts.shape[0])]
+
+
+def pu_radius(n, N):
+    """The patch radius R = 2 sqrt(n/N) (eq. rad_patches)."""
+    return 2.0 * np.sqrt(n / N)
+
+
+def pu_count(a, n, N):
+    """The patch count ceil(a N / n) (eq. num_patches)."""
+    return int(np.ceil(a * N / n))
 
 
 def knn(nodes, queries, n):

@@ -7,6 +7,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -31,6 +32,15 @@ struct rbfsl_ctx {
     bool cached = false;
     double *F = nullptr, *frinv = nullptr;
     int32_t *fpiv = nullptr, *fstep = nullptr, *fstat = nullptr;
+    // RBF-PU (mode RBFSL_STENCIL_PU): patches, their factorizations (the
+    // fields above) and coefficients, and the centres' spatial hash
+    int64_t Mp = 0;
+    double R = 0.0;
+    int ncap = 0, pcap = 0, nmax = 0;
+    double *cx = nullptr, *cy = nullptr, *cz = nullptr, *pd2 = nullptr, *pr2 = nullptr;
+    double *coef = nullptr, *sd2 = nullptr;
+    int32_t *pidx = nullptr, *pcnt = nullptr, *sidx = nullptr;
+    Grid cgrid;
     double *q[2] = {nullptr, nullptr};
     int cur = 0;
     int *status = nullptr;
@@ -212,10 +222,12 @@ void ctx_free(rbfsl_ctx *c) {
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     c->ev.clear();
     void *bufs[] = {c->nx, c->ny, c->nz, c->ex, c->ey, c->ez, c->S, c->s2, c->cidx, c->w,
-                    c->q[0], c->q[1], c->status, c->F, c->frinv, c->fpiv, c->fstep, c->fstat};
+                    c->q[0], c->q[1], c->status, c->F, c->frinv, c->fpiv, c->fstep, c->fstat,
+                    c->cx, c->cy, c->cz, c->pd2, c->pr2, c->coef, c->sd2, c->pidx, c->pcnt, c->sidx};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     grid_free(&c->grid);
+    grid_free(&c->cgrid);
 }
 
 int read_status(rbfsl_ctx *c, int st[ST_WORDS]) {
@@ -256,6 +268,22 @@ void prof_collect(rbfsl_ctx *c) {
     c->ev_used = 0;
 }
 
+PuArgs pu_args(const rbfsl_ctx *c, int64_t m) {
+    PuArgs a{};
+    a.nx = c->nx; a.ny = c->ny; a.nz = c->nz; a.N = c->N;
+    a.cx = c->cx; a.cy = c->cy; a.cz = c->cz; a.Mp = c->Mp;
+    a.R = c->R; a.R2 = c->R * c->R;
+    a.pidx = c->pidx; a.pd2 = c->pd2; a.cnt = c->pcnt;
+    a.ncap = c->ncap; a.nmax = c->nmax; a.L = c->L; a.k = c->k; a.ntr = c->ntr;
+    a.F = c->F; a.rinv = c->frinv; a.stepof = c->fstep; a.fstat = c->fstat;
+    a.coef = c->coef;
+    a.ex = c->ex; a.ey = c->ey; a.ez = c->ez;
+    a.sidx = c->sidx; a.sd2 = c->sd2; a.pcap = c->pcap;
+    a.qin = c->q[c->cur]; a.qout = c->q[1 - c->cur];
+    a.status = c->status; a.step = m;
+    return a;
+}
+
 hipError_t enqueue_step(rbfsl_ctx *c, int64_t m) {
     const StepCoef sc = make_step_coef(c->p, m);
     hipError_t e = prof_mark(c, 0);
@@ -263,6 +291,19 @@ hipError_t enqueue_step(rbfsl_ctx *c, int64_t m) {
     e = launch_trace(c->nx, c->ny, c->nz, c->N, sc, c->ex, c->ey, c->ez, c->status, m, c->stream);
     if (e != hipSuccess) return e;
     if ((e = prof_mark(c, 1)) != hipSuccess) return e;
+    if (c->mode == RBFSL_STENCIL_PU) {
+        // the patches containing each departure point, the patches'
+        // coefficients, the partition-of-unity blend
+        e = launch_knn(c->cgrid, c->Mp, c->ex, c->ey, c->ez, c->N, c->pcap, c->sidx, c->sd2, nullptr,
+                       c->status, m, c->stream);
+        if (e != hipSuccess) return e;
+        if ((e = prof_mark(c, 2)) != hipSuccess) return e;
+        const PuArgs a = pu_args(c, m);
+        if ((e = launch_pu_coef(a, c->stream)) != hipSuccess) return e;
+        if ((e = prof_mark(c, 3)) != hipSuccess) return e;
+        if ((e = launch_pu_eval(a, c->stream)) != hipSuccess) return e;
+        return prof_mark(c, 4);
+    }
     if (c->mode == 0)
         e = launch_knn(c->grid, c->N, c->ex, c->ey, c->ez, c->N, c->n, c->S, nullptr, c->s2, c->status, m, c->stream);
     else
@@ -445,6 +486,119 @@ int rbfsl_create(const double *nodes_xyz, int64_t N, int nodes_on_device, const 
     return RBFSL_OK;
 }
 
+int rbfsl_create_pu(const double *nodes_xyz, int64_t N, int nodes_on_device, const double *centers_xyz,
+                    int64_t Mp, double R, const rbfsl_params *p, void *hip_stream, rbfsl_ctx **out) {
+    if (!out) return RBFSL_E_INVAL;
+    *out = nullptr;
+    if (!p || !nodes_xyz || !centers_xyz) return RBFSL_E_INVAL;
+    if (p->stencil_mode != RBFSL_STENCIL_PU || p->cache_factors != 0 || Mp < 1 || Mp > 0x7fffffffLL ||
+        !(R > 0.0) || !(R < 2.0 + 1e-12) || !isfinite(R))
+        return RBFSL_E_INVAL;
+    rbfsl_params q = *p;
+    q.stencil_mode = 0;
+    int L, k;
+    char msg[256];
+    if (validate_params(N, &q, &L, &k, msg, sizeof msg) != RBFSL_OK) return RBFSL_E_INVAL;
+    const int mL = (L + 1) * (L + 1);
+    rbfsl_ctx *c = new (std::nothrow) rbfsl_ctx();
+    if (!c) return RBFSL_E_NOMEM;
+    c->p = *p;
+    c->p.L = L;
+    c->p.k = k;
+    c->n = p->n; c->L = L; c->k = k;
+    c->ntr = p->n_tracers; c->mode = RBFSL_STENCIL_PU; c->N = N;
+    c->Mp = Mp; c->R = R;
+    // node lists hold up to ncap nodes (about twice the nominal patch size);
+    // a departure point may lie in up to pcap patches
+    c->ncap = (int)std::min<int64_t>(N, std::min<int64_t>(2 * (int64_t)p->n + 64, KNN_CAP));
+    c->pcap = (int)std::min<int64_t>(Mp, 16);
+    c->stream = (hipStream_t)hip_stream;
+    hipError_t e = hipGetDevice(&c->device);
+    const size_t d = sizeof(double);
+    const int64_t nc = c->ncap;
+#define ALLOC(ptr, bytes) if (e == hipSuccess) e = hipMalloc(&(ptr), (bytes))
+    ALLOC(c->nx, d * N); ALLOC(c->ny, d * N); ALLOC(c->nz, d * N);
+    ALLOC(c->ex, d * N); ALLOC(c->ey, d * N); ALLOC(c->ez, d * N);
+    ALLOC(c->cx, d * Mp); ALLOC(c->cy, d * Mp); ALLOC(c->cz, d * Mp);
+    ALLOC(c->pidx, sizeof(int32_t) * Mp * nc); ALLOC(c->pd2, d * Mp * nc);
+    ALLOC(c->pcnt, sizeof(int32_t) * (Mp + 1)); ALLOC(c->pr2, d * Mp);
+    ALLOC(c->sidx, sizeof(int32_t) * N * c->pcap); ALLOC(c->sd2, d * N * c->pcap);
+    ALLOC(c->q[0], d * N * c->ntr); ALLOC(c->q[1], d * N * c->ntr);
+    ALLOC(c->status, sizeof(int) * ST_WORDS);
+#undef ALLOC
+    int code = RBFSL_OK;
+    if (e == hipSuccess) e = upload_points(nodes_xyz, N, nodes_on_device, c->nx, c->ny, c->nz, c->stream);
+    if (e == hipSuccess) e = upload_points(centers_xyz, Mp, nodes_on_device, c->cx, c->cy, c->cz, c->stream);
+    if (e == hipSuccess) e = grid_build(c->nx, c->ny, c->nz, N, c->ncap, &c->grid, c->stream);
+    if (e == hipSuccess) e = grid_build(c->cx, c->cy, c->cz, Mp, c->pcap, &c->cgrid, c->stream);
+    if (e == hipSuccess) e = launch_status_reset(c->status, c->stream);
+    // each patch: the ncap nodes nearest its centre, the cap's prefix counted
+    if (e == hipSuccess)
+        e = launch_knn(c->grid, N, c->cx, c->cy, c->cz, Mp, c->ncap, c->pidx, c->pd2, nullptr, c->status, 0,
+                       c->stream);
+    int *dmax = c->pcnt + Mp;  // scratch word for the largest count
+    if (e == hipSuccess) e = hipMemsetAsync(dmax, 0, sizeof(int), c->stream);
+    PuArgs a = pu_args(c, 0);
+    if (e == hipSuccess) e = launch_pu_count(a, MAX_SYSTEM - mL, c->pcnt, dmax, c->stream);
+    int st[ST_WORDS] = {0, 0, 0, NO_FAIL};
+    int nmax = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(st, c->status, sizeof st, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&nmax, dmax, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess && (st[ST_SEARCH] || nmax < 1 || solve_variant_capacity(nmax + mL) == 0)) code = RBFSL_E_SEARCH;
+    if (e == hipSuccess && code == RBFSL_OK) {
+        // every patch's system, factored once (slots of the largest system)
+        c->nmax = nmax;
+        const size_t Ms = (size_t)(nmax + mL);
+        void **fb[] = {(void **)&c->F, (void **)&c->frinv, (void **)&c->fpiv, (void **)&c->fstep,
+                       (void **)&c->fstat, (void **)&c->coef};
+        const size_t fs[] = {d * Mp * Ms * Ms, d * Mp * Ms, sizeof(int32_t) * Mp * Ms, sizeof(int32_t) * Mp * Ms,
+                             sizeof(int32_t) * Mp, d * Mp * c->ntr * Ms};
+        for (int b = 0; b < 6 && e == hipSuccess; ++b) e = hipMalloc(fb[b], fs[b]);
+        std::vector<double> r2((size_t)Mp, R * R);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->pr2, r2.data(), d * Mp, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) {
+            FactorArgs fa{};
+            fa.s.nx = c->nx; fa.s.ny = c->ny; fa.s.nz = c->nz; fa.s.N = N;
+            fa.s.ex = c->cx; fa.s.ey = c->cy; fa.s.ez = c->cz;
+            fa.s.cx = c->cx; fa.s.cy = c->cy; fa.s.cz = c->cz;
+            fa.s.S = c->pidx; fa.s.s2 = c->pr2; fa.s.cidx = nullptr;
+            fa.s.count = Mp; fa.s.n = nmax; fa.s.L = c->L; fa.s.k = c->k;
+            fa.s.nvar = c->pcnt; fa.s.sstride = nc;
+            fa.s.w = nullptr; fa.s.st_out = nullptr; fa.s.status = c->status; fa.s.step = 0;
+            fa.F = c->F; fa.piv = c->fpiv; fa.rinv = c->frinv; fa.stepof = c->fstep; fa.fstat = c->fstat;
+            e = launch_factor(fa, c->stream);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    }
+    if (e != hipSuccess) code = (e == hipErrorOutOfMemory) ? RBFSL_E_NOMEM : RBFSL_E_DEVICE;
+    if (code != RBFSL_OK) {
+        ctx_free(c);
+        delete c;
+        return code;
+    }
+    *out = c;
+    return RBFSL_OK;
+}
+
+int rbfsl_pu_info(const rbfsl_ctx *c, int64_t *npatch, int32_t *ncap, int32_t *nmax, double *R) {
+    if (!c || c->mode != RBFSL_STENCIL_PU) return RBFSL_E_INVAL;
+    if (npatch) *npatch = c->Mp;
+    if (ncap) *ncap = c->ncap;
+    if (nmax) *nmax = c->nmax;
+    if (R) *R = c->R;
+    return RBFSL_OK;
+}
+
+int rbfsl_debug_patches(rbfsl_ctx *c, int32_t *counts, int32_t *idx) {
+    if (!c || c->mode != RBFSL_STENCIL_PU || !counts || !idx) return RBFSL_E_INVAL;
+    HIP_TRY(c, hipMemcpyAsync(counts, c->pcnt, sizeof(int32_t) * c->Mp, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(idx, c->pidx, sizeof(int32_t) * c->Mp * c->ncap, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return RBFSL_OK;
+}
+
 int rbfsl_set_q(rbfsl_ctx *c, const double *q, int on_device) {
     if (!c || !q) return RBFSL_E_INVAL;
     HIP_TRY(c, hipMemcpyAsync(c->q[c->cur], q, sizeof(double) * c->N * c->ntr,
@@ -546,7 +700,7 @@ int rbfsl_debug_departure(rbfsl_ctx *c, double *xi) {
 }
 
 int rbfsl_debug_stencils(rbfsl_ctx *c, int32_t *idx) {
-    if (!c || !idx) return RBFSL_E_INVAL;
+    if (!c || !idx || c->mode == RBFSL_STENCIL_PU) return RBFSL_E_INVAL;
     if (!c->ran) return fail(c, RBFSL_E_STATE, "no step has run");
     const size_t bytes = sizeof(int32_t) * c->N * c->n;
     if (c->mode == 0) {
@@ -567,7 +721,7 @@ int rbfsl_debug_stencils(rbfsl_ctx *c, int32_t *idx) {
 }
 
 int rbfsl_debug_weights(rbfsl_ctx *c, double *w) {
-    if (!c || !w) return RBFSL_E_INVAL;
+    if (!c || !w || c->mode == RBFSL_STENCIL_PU) return RBFSL_E_INVAL;
     if (!c->ran) return fail(c, RBFSL_E_STATE, "no step has run");
     HIP_TRY(c, hipMemcpyAsync(w, c->w, sizeof(double) * c->N * c->n, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));

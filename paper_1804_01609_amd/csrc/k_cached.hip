@@ -11,12 +11,13 @@
 // unknown, z_k = y_pk r_k, y_i = fma(-u_ik, z_k, y_i) for rows pivoted before
 // step k.  The weights are therefore bit for bit those of refactoring.
 //
-// One wave per evaluation point, positions in pivot order on lanes (R slots):
-// the stored matrix keeps its rows in pivot order, so step k's multipliers
-// are the positions below k of column k and its U entries the positions above
-// it; each stored element is read once, and the kernel is bound by HBM
-// bandwidth: 8 M^2 bytes per point.
+// One wave per evaluation point, positions in pivot order on lanes (R slots),
+// the replay itself in k_replay.h: the stored matrix keeps its rows in pivot
+// order, so step k's multipliers are the positions below k of column k and
+// its U entries the positions above it; each stored element is read once,
+// and the kernel is bound by HBM bandwidth: 8 M^2 bytes per point.
 #include "dev_util.h"
+#include "k_replay.h"
 #include "k_solve.h"
 
 namespace rbfsl {
@@ -83,97 +84,14 @@ __global__ void __launch_bounds__(64) k_solve_cached(CachedArgs A) {
         y[r] = (q < M) ? yl[q] : 0.0;
     });
 
-    const double *F = A.F + K * (int64_t)M * M;
-    const double *rinv = A.rinv + K * M;
-    // Columns are fetched CK steps ahead into registers (double buffered), so
-    // the loads of a whole block are in flight while the previous block runs.
-    constexpr int CK = 8;
-    double cb[CK][R], nb[CK][R];
-    // forward: the elimination's updates of the right-hand side; positions
-    // at or before k are pivoted rows (multiplier 0)
-    auto fetch_fwd = [&](double (&buf)[CK][R], int k0) SI {
-        sfor<0, CK>([&](auto CI) SI {
-            constexpr int c = CI;
-            const int kk = k0 + c;
-            sfor<0, R>([&](auto RI) SI {
-                constexpr int r = RI;
-                const int q = lane + 64 * r;
-                double v = 0.0;
-                if (q > kk && q < M) v = F[(int64_t)kk * M + q];
-                buf[c][r] = v;
-            });
-        });
-    };
-    fetch_fwd(nb, 0);
-    for (int k0 = 0; k0 < M; k0 += CK) {
-        sfor<0, CK>([&](auto CI) SI { sfor<0, R>([&](auto RI) SI { cb[CI][RI] = nb[CI][RI]; }); });
-        if (k0 + CK < M) fetch_fwd(nb, k0 + CK);
-        sfor<0, CK>([&](auto CI) SI {
-            constexpr int c = CI;
-            const int kk = k0 + c;
-            if (kk < M) {
-                const double rk = rinv[kk];
-                const int pl = kk & 63, pr = kk >> 6;
-                double yp = bcast_d(y[0], pl);
-                sfor<1, R>([&](auto RI) SI {
-                    constexpr int r = RI;
-                    const double yr = bcast_d(y[r], pl);
-                    yp = (pr == r) ? yr : yp;
-                });
-                sfor<0, R>([&](auto RI) SI {
-                    constexpr int r = RI;
-                    const int q = lane + 64 * r;
-                    const double l = (q <= kk) ? 0.0 : cb[c][r] * rk;
-                    y[r] = fma(-l, yp, y[r]);
-                });
-            }
-        });
-    }
-    // back substitution; z_k for k < n are the weights
+    // the stored elimination replayed; z_k for k < n are the weights
     bool bad = false;
-    auto fetch_bwd = [&](double (&buf)[CK][R], int k1) SI {  // steps k1, k1-1, ...
-        sfor<0, CK>([&](auto CI) SI {
-            constexpr int c = CI;
-            const int kk = k1 - c;
-            sfor<0, R>([&](auto RI) SI {
-                constexpr int r = RI;
-                const int q = lane + 64 * r;
-                double v = 0.0;
-                if (q < kk) v = F[(int64_t)kk * M + q];
-                buf[c][r] = v;
-            });
-        });
-    };
-    fetch_bwd(nb, M - 1);
-    for (int k1 = M - 1; k1 >= 0; k1 -= CK) {
-        sfor<0, CK>([&](auto CI) SI { sfor<0, R>([&](auto RI) SI { cb[CI][RI] = nb[CI][RI]; }); });
-        if (k1 - CK >= 0) fetch_bwd(nb, k1 - CK);
-        sfor<0, CK>([&](auto CI) SI {
-            constexpr int c = CI;
-            const int kk = k1 - c;
-            if (kk >= 0) {
-                const double rk = rinv[kk];
-                const int pl = kk & 63, pr = kk >> 6;
-                double yk = bcast_d(y[0], pl);
-                sfor<1, R>([&](auto RI) SI {
-                    constexpr int r = RI;
-                    const double yr = bcast_d(y[r], pl);
-                    yk = (pr == r) ? yr : yk;
-                });
-                const double zk = yk * rk;
-                if (kk < n) {
-                    if (lane == 0) A.w[j * n + kk] = zk;
-                    if (!isfinite(zk)) bad = true;
-                }
-                sfor<0, R>([&](auto RI) SI {
-                    constexpr int r = RI;
-                    const int q = lane + 64 * r;
-                    const double yn = fma(-cb[c][r], zk, y[r]);
-                    y[r] = (q < kk) ? yn : y[r];
-                });
-            }
-        });
-    }
+    replay_solve<R>(A.F + K * (int64_t)M * M, A.rinv + K * M, M, lane, y, [&](int kk, double zk) SI {
+        if (kk < n) {
+            if (lane == 0) A.w[j * n + kk] = zk;
+            if (!isfinite(zk)) bad = true;
+        }
+    });
     if (bad && lane == 0) {
         atomicAdd(&A.status[ST_NONFINITE], 1);
         atomicMin(&A.status[ST_FAILSTEP], (int)A.step);

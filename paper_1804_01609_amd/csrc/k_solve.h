@@ -608,12 +608,13 @@ __attribute__((amdgpu_waves_per_eu(WPE, WPE))) k_factor(FactorArgs FA) {
     const SolveArgs &A = FA.s;
     const int64_t j = blockIdx.x;
     const int t = threadIdx.x;
-    const int n = A.n;
-    const int M = n + (A.L + 1) * (A.L + 1);
+    // slots sized for the largest system; this system has nvar[row] nodes
+    const int M = A.n + (A.L + 1) * (A.L + 1);
     const int64_t row = A.cidx ? (int64_t)A.cidx[j] : j;
+    const int n = A.nvar ? A.nvar[row] : A.n;
     SysIn in;
     in.nx = A.nx; in.ny = A.ny; in.nz = A.nz; in.N = A.N;
-    in.S = A.S + row * n;
+    in.S = A.S + row * (A.sstride ? A.sstride : (int64_t)A.n);
     in.xe[0] = A.ex[j]; in.xe[1] = A.ey[j]; in.xe[2] = A.ez[j];
     if (A.cx) {
         in.ctr[0] = A.cx[row]; in.ctr[1] = A.cy[row]; in.ctr[2] = A.cz[row];

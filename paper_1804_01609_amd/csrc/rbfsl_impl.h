@@ -104,6 +104,11 @@ struct SolveArgs {
     int32_t *st_out;             // optional per-stencil status
     int *status;
     int64_t step;
+    // factor-only use with stencils of different sizes (RBF-PU patches):
+    // stencil t has nvar[row(t)] <= n nodes, stored with row stride sstride
+    // (null / 0: every stencil has n nodes, stride n)
+    const int32_t *nvar;
+    int64_t sstride;
 };
 hipError_t launch_solve(const SolveArgs &a, hipStream_t s);
 
@@ -113,7 +118,8 @@ hipError_t launch_solve(const SolveArgs &a, hipStream_t s);
 // RBFSL_E_SINGULAR.
 struct FactorArgs {
     SolveArgs s;
-    double *F;        // count x M x M
+    double *F;        // count x M x M (M = s.n + (L+1)^2: the largest system;
+                      // a smaller one is stored column-major in its slot's start)
     int32_t *piv;     // count x M
     double *rinv;     // count x M
     int32_t *stepof;  // count x M
@@ -142,6 +148,43 @@ struct CachedArgs {
 };
 hipError_t launch_solve_cached(const CachedArgs &a, hipStream_t s);
 int solve_variant_capacity(int M);  // capacity of the variant chosen for M (0: unsupported)
+
+// RBF-PU (Sections 2.3 and 3.3.3).  Patch l holds the cnt[l] nodes
+// pidx[l*ncap ..] (its stencil, in (d^2, index) order), its system factored
+// as FactorArgs stores it (slots of Mmax = nmax + (L+1)^2), centre c[l],
+// squared radius R2.
+struct PuArgs {
+    const double *nx, *ny, *nz;
+    int64_t N;
+    const double *cx, *cy, *cz;  // patch centres
+    int64_t Mp;                  // patch count
+    double R, R2;                // radius, R * R
+    const int32_t *pidx;         // Mp x ncap node lists
+    const double *pd2;           // Mp x ncap squared distances (counting only)
+    const int32_t *cnt;          // Mp node counts
+    int ncap, nmax, L, k, ntr;
+    const double *F, *rinv;
+    const int32_t *stepof, *fstat;
+    double *coef;                // Mp x ntr x Mmax: [c; d] of every patch and tracer
+    // departure points and the patches that contain them
+    const double *ex, *ey, *ez;
+    const int32_t *sidx;         // N x pcap patch indices, (d^2, l) order
+    const double *sd2;           // N x pcap squared distances
+    int pcap;
+    const double *qin;           // ntr x N
+    double *qout;                // ntr x N
+    int *status;
+    int64_t step;
+};
+// node counts of the patches (d^2 < R2 among the ncap nearest); a full
+// list, a count over nmax_allowed or an empty patch is reported in status
+// as a failed search; *nmax (device int) receives the largest count
+hipError_t launch_pu_count(const PuArgs &a, int nmax_allowed, int32_t *cnt, int *nmax, hipStream_t s);
+// every patch's coefficients for every tracer, from the stored factorizations
+hipError_t launch_pu_coef(const PuArgs &a, hipStream_t s);
+// q at the departure points: the B-spline partition of unity over the
+// patches that contain each point (eq. PU_interp)
+hipError_t launch_pu_eval(const PuArgs &a, hipStream_t s);
 
 hipError_t launch_apply(const double *w, const int32_t *S, const int32_t *cidx, int64_t N, int n,
                         int ntr, const double *qin, double *qout, const int *status,

@@ -51,6 +51,31 @@ def test_invalid_arguments_are_rejected_without_a_device():
     assert not out.value
 
 
+def test_pu_arguments_are_rejected_without_a_device():
+    import numpy as np
+    L = rb.lib()
+    out = ctypes.c_void_p()
+    X = np.zeros((100, 3))
+    C = np.zeros((10, 3))
+    vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    good = rb.make_params(31, 3, 2, rb.STENCIL_PU)
+    # RBF-PU needs its own stencil mode; plain create refuses it
+    assert L.rbfsl_create(vp(X), 100, 0, ctypes.byref(good), None, ctypes.byref(out)) == rb.RBFSL_E_INVAL
+    p0 = rb.make_params(31, 3, 2, 0)
+    assert L.rbfsl_create_pu(vp(X), 100, 0, vp(C), 10, 0.5, ctypes.byref(p0), None,
+                             ctypes.byref(out)) == rb.RBFSL_E_INVAL
+    for R in (0.0, -1.0, 3.0, float("nan")):
+        assert L.rbfsl_create_pu(vp(X), 100, 0, vp(C), 10, R, ctypes.byref(good), None,
+                                 ctypes.byref(out)) == rb.RBFSL_E_INVAL
+    assert L.rbfsl_create_pu(vp(X), 100, 0, None, 10, 0.5, ctypes.byref(good), None,
+                             ctypes.byref(out)) == rb.RBFSL_E_INVAL
+    assert L.rbfsl_create_pu(vp(X), 100, 0, vp(C), 0, 0.5, ctypes.byref(good), None,
+                             ctypes.byref(out)) == rb.RBFSL_E_INVAL
+    assert L.rbfsl_pu_info(None, None, None, None, None) == rb.RBFSL_E_INVAL
+    assert not out.value
+    assert rb.pu_radius(84, 23042) == 2.0 * np.sqrt(84 / 23042) and rb.pu_count(2.5, 84, 23042) == 686
+
+
 def _c_layout(exprs):
     """sizeof/offsetof values of header types, from a tiny C program built with gcc."""
     import subprocess

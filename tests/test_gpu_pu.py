@@ -1,0 +1,130 @@
+"""GPU parity of the RBF-PU step (Sections 2.3 and 3.3.3) against the oracle:
+patch membership bit for bit, q after one step and after full runs bit for
+bit (several tracers, RK4 and Fehlberg RK5, solid-body and NL2010 flows), the
+full C2 node count on sampled nodes, and the failure paths (a departure
+point in no patch; bad arguments)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1804_01609_amd as rb
+from paper_1804_01609_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def setup(N, n, a=2.5):
+    X = W.fibonacci_nodes(N)
+    R = rb.pu_radius(n, N)
+    C = W.fibonacci_nodes(rb.pu_count(a, n, N))
+    assert R == oracle.pu_radius(n, N)
+    return X, C, R
+
+
+def params(n, L, k, vel, vp, dt, ntr=1, rk=rb.RK4):
+    g = rb.make_params(n, L, k, rb.STENCIL_PU, vel, vp, dt, 0.0, ntr, rk)
+    o = oracle.make_params(n, L, k, 0, vel, vp, dt, 0.0, ntr, rk)
+    return g, o
+
+
+def test_patch_membership_bit_exact():
+    say("[pu] patches N=2562 n=31")
+    X, C, R = setup(2562, 31)
+    g, _ = params(31, 3, 2, rb.VEL_SOLID_BODY, W.tc1_vp(), 0.1)
+    with rb.PuTransport(X, C, R, g) as tr:
+        counts, lists = tr.patches()
+        info = tr.info()
+    oc, off, idx = oracle.pu_patches(X, C, R)
+    assert info["patches"] == C.shape[0] and info["nmax"] == oc.max()
+    assert np.array_equal(counts, oc)
+    for l in range(C.shape[0]):
+        assert np.array_equal(lists[l], idx[off[l]:off[l + 1]])
+
+
+def test_one_step_bit_exact():
+    say("[pu] one step N=2562")
+    X, C, R = setup(2562, 31)
+    g, o = params(31, 3, 2, rb.VEL_SOLID_BODY, W.tc1_vp(), 0.2)
+    q0 = W.c1_bump(X)[None]
+    with rb.PuTransport(X, C, R, g) as tr:
+        tr.set_q(q0)
+        tr.step()
+        xi, q1 = tr.departure(), tr.get_q()
+    ref = oracle.pu_step(X, C, R, oracle.pu_patches(X, C, R), o, 0, np.arange(X.shape[0]), q0)
+    assert np.all(ref["status"] == 0)
+    assert np.array_equal(xi, ref["xi"])
+    assert np.array_equal(q1, ref["q"])
+
+
+@pytest.mark.parametrize("N,n,L,k,vel,rk,ntr,steps", [
+    (1024, 31, 3, 2, rb.VEL_SOLID_BODY, rb.RK4, 2, 6),
+    (4096, 56, 4, 2, rb.VEL_NL2010, rb.RK5_FEHLBERG, 1, 4),
+    (2562, 84, 5, 3, rb.VEL_DEFORM, rb.RK4, 3, 3),
+])
+def test_runs_bit_exact(N, n, L, k, vel, rk, ntr, steps):
+    say(f"[pu] run N={N} n={n} L={L} k={k} vel={vel} rk={rk} ntr={ntr}")
+    X, C, R = setup(N, n)
+    vp = {rb.VEL_SOLID_BODY: W.tc1_vp(), rb.VEL_NL2010: W.nl2010_vp(), rb.VEL_DEFORM: W.deform_vp(5.0)}[vel]
+    dt = 5.0 / 64 if vel != rb.VEL_SOLID_BODY else vp[0] / 96
+    g, o = params(n, L, k, vel, vp, dt, ntr, rk)
+    q0 = np.stack([W.c1_bump(X), W.gaussian_bells(X), np.ones(N)][:ntr])
+    with rb.PuTransport(X, C, R, g) as tr:
+        tr.set_q(q0)
+        tr.run(steps)
+        q = tr.get_q()
+        assert tr.state()[0] == steps
+    qo, st, _ = oracle.pu_run(X, C, R, o, q0, steps)
+    assert st == 0
+    assert np.abs(q - qo).max() <= 1e-9
+    assert np.array_equal(q, qo), "q differs in the last bits"
+
+
+def test_c2_size_sampled_nodes_bit_exact():
+    # the full C2 node set (N = 40,962, n = 84, L = 5, k = 3, a = 2.5): every
+    # patch's coefficients in the oracle, sampled departure points compared
+    say("[pu] C2 size, sampled")
+    X, C, R = setup(40962, 84)
+    g, o = params(84, 5, 3, rb.VEL_DEFORM, W.deform_vp(5.0), 5.0 / 480)
+    q0 = W.two_gaussians(X)[None]
+    with rb.PuTransport(X, C, R, g) as tr:
+        tr.set_q(q0)
+        tr.step()
+        q1 = tr.get_q()
+    jl = np.random.default_rng(7).choice(X.shape[0], 1500, replace=False)
+    ref = oracle.pu_step(X, C, R, oracle.pu_patches(X, C, R), o, 0, jl, q0)
+    assert np.all(ref["status"] == 0)
+    assert np.array_equal(q1[:, jl], ref["q"])
+
+
+def test_point_in_no_patch_fails_the_step_and_keeps_the_state():
+    say("[pu] uncovered")
+    X = W.fibonacci_nodes(1000)
+    C = W.fibonacci_nodes(6)
+    R = rb.pu_radius(31, 1000)
+    g, _ = params(31, 3, 2, rb.VEL_ZERO, (), 0.1)
+    q0 = np.ones((1, 1000))
+    with rb.PuTransport(X, C, R, g) as tr:
+        tr.set_q(q0)
+        with pytest.raises(rb.RbfslError) as e:
+            tr.step()
+        assert e.value.code == rb.RBFSL_E_SEARCH
+        assert tr.state()[0] == 0
+        assert np.array_equal(tr.get_q(), q0)
+        with pytest.raises(rb.RbfslError):
+            tr.weights()
+
+
+def test_patch_too_large_for_the_solver_is_refused():
+    say("[pu] oversize patch")
+    X = W.fibonacci_nodes(2000)
+    C = W.fibonacci_nodes(40)
+    g, _ = params(31, 3, 2, rb.VEL_ZERO, (), 0.1)
+    with pytest.raises(rb.RbfslError) as e:
+        rb.PuTransport(X, C, 0.9, g)  # caps of ~400 nodes
+    assert e.value.code == rb.RBFSL_E_SEARCH
