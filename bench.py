@@ -16,6 +16,9 @@ Sections (all by default):
              stepped one after another on the plain path;
   centre  -- the paper's centre-point stencils with every node's factorization
              computed once and replayed each step (same C2 workload);
+  pu      -- the same workload interpolated by RBF-PU (patches factored once;
+             per step: patch search, patch coefficients, partition-of-unity
+             blend);
   served  -- a Poisson stream of transport requests (arrival rate 0.8 x the
              capacity calibrated on the request mix) through the pool's
              continuous-batching loop under a 200 GB HBM budget: p50/p99
@@ -112,7 +115,7 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--sections", default="plain,centre,batched,served")
+    ap.add_argument("--sections", default="plain,centre,pu,batched,served")
     ap.add_argument("--batched-steps", type=int, default=24)
     ap.add_argument("--served-requests", type=int, default=10)
     ap.add_argument("--served-step-scale", type=float, default=0.25,
@@ -198,6 +201,9 @@ def main():
         out["centre"] = bench_centre(cfg, X, q0, sync)
         say(f"centre (cached factors): {out['centre']['value']:.4g} interpolations/s, "
             f"{out['centre']['ms_per_step']:.3f} ms/step")
+    if "pu" in sections:
+        out["pu"] = bench_pu(cfg, X, q0, sync)
+        say(f"RBF-PU: {out['pu']['value']:.4g} interpolations/s, {out['pu']['ms_per_step']:.3f} ms/step")
     if "batched" in sections:
         out["batched"] = bench_batched(args.batched_steps, sync)
         say(f"batched: {out['batched']['value']:.4g} interpolations/s "
@@ -243,6 +249,49 @@ def bench_centre(cfg, X, q0, sync, steps=100):
                                "achieved": bytes_solve / (solve_ms * 1e-3) / 1e9, "peak": 8000.0,
                                "unit": "GB/s", "frac": bytes_solve / (solve_ms * 1e-3) / 8e12,
                                "algorithmic_bytes_per_launch": bytes_solve}}
+
+
+def bench_pu(cfg, X, q0, sync, steps=200, a=2.5):
+    """C2's nodes, flow and (n, L, k) with RBF-PU interpolation (Sections 2.3
+    and 3.3.3): ceil(a N / n) patches of radius 2 sqrt(n/N) around
+    quasi-uniform centres, factored once at create; per step the patch search
+    of every departure point, every patch's coefficients from its stored
+    factorization (HBM: 8 M_l^2 bytes per patch and tracer) and the
+    partition-of-unity blend (FP64 ALU: per containing patch, n_l PHS terms and
+    (L+1)^2 basis terms)."""
+    N, n, L, k = cfg["N"], cfg["n"], cfg["L"], cfg["k"]
+    R = rb.pu_radius(n, N)
+    C = W.fibonacci_nodes(rb.pu_count(a, n, N))
+    p = rb.make_params(n, L, k, rb.STENCIL_PU, cfg["vel_id"], cfg["vp"], cfg["dt"], 0.0, cfg["ntr"])
+    sync()
+    t = time.perf_counter()
+    tr = rb.PuTransport(X, C, R, p)
+    sync()
+    create_s = time.perf_counter() - t
+    counts, _ = tr.patches()
+    tr.set_q(q0)
+    tr.run(2)
+    tr.profile(True)
+    sync()
+    t = time.perf_counter()
+    tr.run(steps)
+    sync()
+    dt = time.perf_counter() - t
+    ph, nrec = tr.phase_times()
+    tr.close()
+    mL = (L + 1) ** 2
+    coef_ms, eval_ms = ph[2] / max(nrec, 1), ph[3] / max(nrec, 1)
+    coef_bytes = 8.0 * float(((counts.astype(np.float64) + mL) ** 2).sum()) * cfg["ntr"]
+    return {"workload": f"{cfg['name']}-rbfpu-a{a}", "patches": int(C.shape[0]), "R": R,
+            "nodes_per_patch": [int(counts.min()), float(counts.mean()), int(counts.max())],
+            "steps": steps, "value": N * steps / dt, "unit": "interpolations/s", "ms_per_step": 1e3 * dt / steps,
+            "create_s_incl_factorization": create_s,
+            "phase_ms_per_step": {nm: ph[i] / max(nrec, 1)
+                                  for i, nm in enumerate(["trace", "patch_search", "coef", "eval"])},
+            "roofline_coef": {"kernel": "k_pu_coef", "bound": "hbm",
+                              "achieved": coef_bytes / (coef_ms * 1e-3) / 1e9, "peak": 8000.0, "unit": "GB/s",
+                              "frac": coef_bytes / (coef_ms * 1e-3) / 8e12,
+                              "algorithmic_bytes_per_launch": coef_bytes}}
 
 
 def _run_inputs(r):
