@@ -120,8 +120,9 @@ int rbfsl_create(const double *nodes_xyz, int64_t N, int nodes_on_device,
  * Fails with RBFSL_E_SEARCH when a patch is empty, holds more nodes than a
  * system of rbfsl_max_system() unknowns allows, or more than its node list
  * (about 2n + 64 nodes); a step fails with RBFSL_E_SEARCH when a departure
- * point lies in no patch or in more than 16, and with RBFSL_E_SINGULAR when a
- * patch it uses has a singular system.  rbfsl_debug_stencils and
+ * point lies in no patch or in more patches than its list holds (twice the
+ * mean overlap Mp R^2 / 4 plus 3, at least 8, at most 32), and with
+ * RBFSL_E_SINGULAR when a patch it uses has a singular system.  rbfsl_debug_stencils and
  * rbfsl_debug_weights do not apply (RBFSL_E_INVAL). */
 enum { RBFSL_STENCIL_PU = 2 };
 int rbfsl_create_pu(const double *nodes_xyz, int64_t N, int nodes_on_device, const double *centers_xyz,

@@ -38,7 +38,7 @@ struct rbfsl_ctx {
     double R = 0.0;
     int ncap = 0, pcap = 0, nmax = 0;
     double *cx = nullptr, *cy = nullptr, *cz = nullptr, *pd2 = nullptr, *pr2 = nullptr;
-    double *coef = nullptr, *sd2 = nullptr;
+    double *coef = nullptr, *sd2 = nullptr, *sval = nullptr;
     int32_t *pidx = nullptr, *pcnt = nullptr, *sidx = nullptr;
     Grid cgrid;
     double *q[2] = {nullptr, nullptr};
@@ -223,7 +223,7 @@ void ctx_free(rbfsl_ctx *c) {
     c->ev.clear();
     void *bufs[] = {c->nx, c->ny, c->nz, c->ex, c->ey, c->ez, c->S, c->s2, c->cidx, c->w,
                     c->q[0], c->q[1], c->status, c->F, c->frinv, c->fpiv, c->fstep, c->fstat,
-                    c->cx, c->cy, c->cz, c->pd2, c->pr2, c->coef, c->sd2, c->pidx, c->pcnt, c->sidx};
+                    c->cx, c->cy, c->cz, c->pd2, c->pr2, c->coef, c->sd2, c->sval, c->pidx, c->pcnt, c->sidx};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     grid_free(&c->grid);
@@ -279,7 +279,7 @@ PuArgs pu_args(const rbfsl_ctx *c, int64_t m) {
     a.coef = c->coef;
     a.ex = c->ex; a.ey = c->ey; a.ez = c->ez;
     a.sidx = c->sidx; a.sd2 = c->sd2; a.pcap = c->pcap;
-    a.qin = c->q[c->cur]; a.qout = c->q[1 - c->cur];
+    a.qin = c->q[c->cur]; a.qout = c->q[1 - c->cur]; a.sval = c->sval;
     a.status = c->status; a.step = m;
     return a;
 }
@@ -294,11 +294,9 @@ hipError_t enqueue_step(rbfsl_ctx *c, int64_t m) {
     if (c->mode == RBFSL_STENCIL_PU) {
         // the patches containing each departure point, the patches'
         // coefficients, the partition-of-unity blend
-        e = launch_knn(c->cgrid, c->Mp, c->ex, c->ey, c->ez, c->N, c->pcap, c->sidx, c->sd2, nullptr,
-                       c->status, m, c->stream);
-        if (e != hipSuccess) return e;
-        if ((e = prof_mark(c, 2)) != hipSuccess) return e;
         const PuArgs a = pu_args(c, m);
+        if ((e = launch_pu_search(a, c->cgrid, c->stream)) != hipSuccess) return e;
+        if ((e = prof_mark(c, 2)) != hipSuccess) return e;
         if ((e = launch_pu_coef(a, c->stream)) != hipSuccess) return e;
         if ((e = prof_mark(c, 3)) != hipSuccess) return e;
         if ((e = launch_pu_eval(a, c->stream)) != hipSuccess) return e;
@@ -509,9 +507,11 @@ int rbfsl_create_pu(const double *nodes_xyz, int64_t N, int nodes_on_device, con
     c->ntr = p->n_tracers; c->mode = RBFSL_STENCIL_PU; c->N = N;
     c->Mp = Mp; c->R = R;
     // node lists hold up to ncap nodes (about twice the nominal patch size);
-    // a departure point may lie in up to pcap patches
+    // a departure point may lie in up to pcap patches: about twice the mean
+    // overlap Mp R^2 / 4 (area of the caps over the sphere's) plus 3, 8..32
     c->ncap = (int)std::min<int64_t>(N, std::min<int64_t>(2 * (int64_t)p->n + 64, KNN_CAP));
-    c->pcap = (int)std::min<int64_t>(Mp, 16);
+    const double overlap = (double)Mp * R * R / 4.0;
+    c->pcap = (int)std::min<int64_t>(Mp, std::max(8, std::min(32, (int)ceil(2.0 * overlap) + 3)));
     c->stream = (hipStream_t)hip_stream;
     hipError_t e = hipGetDevice(&c->device);
     const size_t d = sizeof(double);
@@ -523,6 +523,7 @@ int rbfsl_create_pu(const double *nodes_xyz, int64_t N, int nodes_on_device, con
     ALLOC(c->pidx, sizeof(int32_t) * Mp * nc); ALLOC(c->pd2, d * Mp * nc);
     ALLOC(c->pcnt, sizeof(int32_t) * (Mp + 1)); ALLOC(c->pr2, d * Mp);
     ALLOC(c->sidx, sizeof(int32_t) * N * c->pcap); ALLOC(c->sd2, d * N * c->pcap);
+    ALLOC(c->sval, d * N * c->pcap * c->ntr);
     ALLOC(c->q[0], d * N * c->ntr); ALLOC(c->q[1], d * N * c->ntr);
     ALLOC(c->status, sizeof(int) * ST_WORDS);
 #undef ALLOC

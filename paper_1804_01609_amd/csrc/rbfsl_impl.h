@@ -168,11 +168,12 @@ struct PuArgs {
     double *coef;                // Mp x ntr x Mmax: [c; d] of every patch and tracer
     // departure points and the patches that contain them
     const double *ex, *ey, *ez;
-    const int32_t *sidx;         // N x pcap patch indices, (d^2, l) order
-    const double *sd2;           // N x pcap squared distances
+    int32_t *sidx;               // N x pcap patch indices, (d^2, l) order
+    double *sd2;                 // N x pcap squared distances (+inf past the last)
     int pcap;
     const double *qin;           // ntr x N
     double *qout;                // ntr x N
+    double *sval;                // pcap x ntr x N: each containing patch's value
     int *status;
     int64_t step;
 };
@@ -180,6 +181,9 @@ struct PuArgs {
 // list, a count over nmax_allowed or an empty patch is reported in status
 // as a failed search; *nmax (device int) receives the largest count
 hipError_t launch_pu_count(const PuArgs &a, int nmax_allowed, int32_t *cnt, int *nmax, hipStream_t s);
+// the patches containing each departure point (d^2 < R2), through the
+// spatial hash of the centres `cg`; more than pcap is a failed search
+hipError_t launch_pu_search(const PuArgs &a, const Grid &cg, hipStream_t s);
 // every patch's coefficients for every tracer, from the stored factorizations
 hipError_t launch_pu_coef(const PuArgs &a, hipStream_t s);
 // q at the departure points: the B-spline partition of unity over the
