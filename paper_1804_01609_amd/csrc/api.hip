@@ -38,7 +38,7 @@ struct rbfsl_ctx {
     double R = 0.0;
     int ncap = 0, pcap = 0, nmax = 0;
     double *cx = nullptr, *cy = nullptr, *cz = nullptr, *pd2 = nullptr, *pr2 = nullptr;
-    double *coef = nullptr, *sd2 = nullptr, *sval = nullptr;
+    double *coef = nullptr, *sd2 = nullptr, *sval = nullptr, *ploc = nullptr;
     int32_t *pidx = nullptr, *pcnt = nullptr, *sidx = nullptr;
     Grid cgrid;
     double *q[2] = {nullptr, nullptr};
@@ -223,7 +223,7 @@ void ctx_free(rbfsl_ctx *c) {
     c->ev.clear();
     void *bufs[] = {c->nx, c->ny, c->nz, c->ex, c->ey, c->ez, c->S, c->s2, c->cidx, c->w,
                     c->q[0], c->q[1], c->status, c->F, c->frinv, c->fpiv, c->fstep, c->fstat,
-                    c->cx, c->cy, c->cz, c->pd2, c->pr2, c->coef, c->sd2, c->sval, c->pidx, c->pcnt, c->sidx};
+                    c->cx, c->cy, c->cz, c->pd2, c->pr2, c->coef, c->sd2, c->sval, c->ploc, c->pidx, c->pcnt, c->sidx};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     grid_free(&c->grid);
@@ -273,7 +273,7 @@ PuArgs pu_args(const rbfsl_ctx *c, int64_t m) {
     a.nx = c->nx; a.ny = c->ny; a.nz = c->nz; a.N = c->N;
     a.cx = c->cx; a.cy = c->cy; a.cz = c->cz; a.Mp = c->Mp;
     a.R = c->R; a.R2 = c->R * c->R;
-    a.pidx = c->pidx; a.pd2 = c->pd2; a.cnt = c->pcnt;
+    a.pidx = c->pidx; a.pd2 = c->pd2; a.cnt = c->pcnt; a.ploc = c->ploc;
     a.ncap = c->ncap; a.nmax = c->nmax; a.L = c->L; a.k = c->k; a.ntr = c->ntr;
     a.F = c->F; a.rinv = c->frinv; a.stepof = c->fstep; a.fstat = c->fstat;
     a.coef = c->coef;
@@ -520,7 +520,7 @@ int rbfsl_create_pu(const double *nodes_xyz, int64_t N, int nodes_on_device, con
     ALLOC(c->nx, d * N); ALLOC(c->ny, d * N); ALLOC(c->nz, d * N);
     ALLOC(c->ex, d * N); ALLOC(c->ey, d * N); ALLOC(c->ez, d * N);
     ALLOC(c->cx, d * Mp); ALLOC(c->cy, d * Mp); ALLOC(c->cz, d * Mp);
-    ALLOC(c->pidx, sizeof(int32_t) * Mp * nc); ALLOC(c->pd2, d * Mp * nc);
+    ALLOC(c->pidx, sizeof(int32_t) * Mp * nc); ALLOC(c->pd2, d * Mp * nc); ALLOC(c->ploc, d * Mp * nc * 3);
     ALLOC(c->pcnt, sizeof(int32_t) * (Mp + 1)); ALLOC(c->pr2, d * Mp);
     ALLOC(c->sidx, sizeof(int32_t) * N * c->pcap); ALLOC(c->sd2, d * N * c->pcap);
     ALLOC(c->sval, d * N * c->pcap * c->ntr);
@@ -571,6 +571,7 @@ int rbfsl_create_pu(const double *nodes_xyz, int64_t N, int nodes_on_device, con
             fa.F = c->F; fa.piv = c->fpiv; fa.rinv = c->frinv; fa.stepof = c->fstep; fa.fstat = c->fstat;
             e = launch_factor(fa, c->stream);
         }
+        if (e == hipSuccess) e = launch_pu_local(pu_args(c, 0), c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     }
     if (e != hipSuccess) code = (e == hipErrorOutOfMemory) ? RBFSL_E_NOMEM : RBFSL_E_DEVICE;

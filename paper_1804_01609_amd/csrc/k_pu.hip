@@ -140,6 +140,37 @@ hipError_t launch_pu_search(const PuArgs &a, const Grid &cg, hipStream_t s) {
     return hipGetLastError();
 }
 
+// one thread per (patch, node slot): the node's coordinates in the patch's
+// frame, y = (x - c) / s with s = sqrt(R2), as the patch's assembly and
+// every evaluation compute them
+__global__ void __launch_bounds__(256) k_pu_local(PuArgs A) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= A.Mp * A.ncap) return;
+    const int64_t l = t / A.ncap;
+    const int b = (int)(t - l * A.ncap);
+    if (b >= A.cnt[l]) return;
+    const double ctr[3] = {A.cx[l], A.cy[l], A.cz[l]};
+    const double s = (A.R2 > 0.0) ? sqrt(A.R2) : 1.0;
+    const double inv_s = 1.0 / s;
+    double e1[3], e2[3];
+    frame3(ctr, e1, e2);
+    const int g = A.pidx[l * A.ncap + b];
+    const double x[3] = {A.nx[g], A.ny[g], A.nz[g]};
+    double y[3], al, be, u;
+    local3(x, ctr, e1, e2, inv_s, y, al, be, u);
+    double *o = A.ploc + t * 3;
+    o[0] = y[0];
+    o[1] = y[1];
+    o[2] = y[2];
+}
+
+hipError_t launch_pu_local(const PuArgs &a, hipStream_t s) {
+    const int64_t n = a.Mp * a.ncap;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pu_local, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 template <int R>
 __global__ void __launch_bounds__(64) k_pu_coef(PuArgs A) {
     __shared__ double yl[64 * R];
@@ -209,19 +240,16 @@ __global__ void __launch_bounds__(256) k_pu_patch_eval(PuArgs A) {
     double yx[3], al, be, u;
     local3(xe, ctr, e1, e2, inv_s, yx, al, be, u);
     const int n = A.cnt[l];
-    const int32_t *S = A.pidx + l * A.ncap;
+    const double *yl = A.ploc + l * A.ncap * 3;  // the nodes' local coordinates
     for (int t0 = 0; t0 < A.ntr; t0 += PU_TB) {
         const int tb = (A.ntr - t0 < PU_TB) ? A.ntr - t0 : PU_TB;
         const double *cf = A.coef + (l * A.ntr + t0) * Ms;
         double acc[PU_TB] = {0.0, 0.0, 0.0, 0.0};
-        // unrolled so that several nodes' gathers and square roots are in
+        // unrolled so that several nodes' loads and square roots are in
         // flight; the fma chain keeps its order
 #pragma unroll 4
         for (int b = 0; b < n; ++b) {
-            const int g = S[b];
-            const double x[3] = {A.nx[g], A.ny[g], A.nz[g]};
-            double yb[3], ab, bb, ub;
-            local3(x, ctr, e1, e2, inv_s, yb, ab, bb, ub);
+            const double *yb = yl + 3 * b;
             const double d0 = yb[0] - yx[0], d1 = yb[1] - yx[1], d2 = yb[2] - yx[2];
             const double ph = phs((d0 * d0 + d1 * d1) + d2 * d2, k);
             for (int t = 0; t < tb; ++t) acc[t] = fma(cf[t * Ms + b], ph, acc[t]);

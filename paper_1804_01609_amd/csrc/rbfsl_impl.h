@@ -162,6 +162,7 @@ struct PuArgs {
     const int32_t *pidx;         // Mp x ncap node lists
     const double *pd2;           // Mp x ncap squared distances (counting only)
     const int32_t *cnt;          // Mp node counts
+    double *ploc;                // Mp x ncap x 3: the nodes' local coordinates in their patch's frame
     int ncap, nmax, L, k, ntr;
     const double *F, *rinv;
     const int32_t *stepof, *fstat;
@@ -184,6 +185,8 @@ hipError_t launch_pu_count(const PuArgs &a, int nmax_allowed, int32_t *cnt, int 
 // the patches containing each departure point (d^2 < R2), through the
 // spatial hash of the centres `cg`; more than pcap is a failed search
 hipError_t launch_pu_search(const PuArgs &a, const Grid &cg, hipStream_t s);
+// the local coordinates of every patch's nodes (fixed: computed at create)
+hipError_t launch_pu_local(const PuArgs &a, hipStream_t s);
 // every patch's coefficients for every tracer, from the stored factorizations
 hipError_t launch_pu_coef(const PuArgs &a, hipStream_t s);
 // q at the departure points: the B-spline partition of unity over the
