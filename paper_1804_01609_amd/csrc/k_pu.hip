@@ -200,7 +200,9 @@ __global__ void __launch_bounds__(64) k_pu_coef(PuArgs A) {
         y[r] = (p < M) ? yl[p] : 0.0;
     });
     double *coef = A.coef + ((int64_t)l * A.ntr + tr) * Ms;
-    replay_solve<R>(A.F + l * (int64_t)Ms * Ms, A.rinv + l * Ms, M, lane, y, [&](int kk, double zk) SI {
+    // few waves (one per patch and tracer): a deeper prefetch than the
+    // cached-factor kernel's keeps more of HBM busy
+    replay_solve<R, 16>(A.F + l * (int64_t)Ms * Ms, A.rinv + l * Ms, M, lane, y, [&](int kk, double zk) SI {
         if (lane == 0) coef[kk] = zk;
     });
 }

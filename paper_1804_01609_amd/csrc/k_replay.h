@@ -13,24 +13,26 @@
 // Positions q = lane + 64 r sit on lanes (R slots); each stored element is
 // read once (8 M^2 bytes per solve), with the columns fetched CK steps ahead
 // into registers (double buffered) so that a block's loads are in flight
-// while the previous block runs.
+// while the previous block runs (a larger CK keeps more bytes in flight per
+// wave, for launches with few waves, at the cost of 4 CK R registers).
 #include "dev_util.h"
 
 namespace rbfsl {
 
 // y: the right-hand side at this lane's positions (pivot order); out(kk, zk)
 // is called for every unknown kk from M-1 down to 0, zk wave-uniform.
-template <int R, typename Out>
+template <int R, int CK = 8, typename Out>
 __device__ __forceinline__ void replay_solve(const double *F, const double *rinv, const int M,
                                              const int lane, double (&y)[R], Out &&out) {
-    constexpr int CK = 8;
     double cb[CK][R], nb[CK][R];
+    double cr[CK], nr[CK];  // the reciprocals of the same steps, fetched with the columns
     // forward: the elimination's updates of the right-hand side; positions
     // at or before k are pivoted rows (multiplier 0)
-    auto fetch_fwd = [&](double (&buf)[CK][R], int k0) SI {
+    auto fetch_fwd = [&](double (&buf)[CK][R], double (&rb)[CK], int k0) SI {
         sfor<0, CK>([&](auto CI) SI {
             constexpr int c = CI;
             const int kk = k0 + c;
+            rb[c] = (kk < M) ? rinv[kk] : 0.0;
             sfor<0, R>([&](auto RI) SI {
                 constexpr int r = RI;
                 const int q = lane + 64 * r;
@@ -40,15 +42,18 @@ __device__ __forceinline__ void replay_solve(const double *F, const double *rinv
             });
         });
     };
-    fetch_fwd(nb, 0);
+    fetch_fwd(nb, nr, 0);
     for (int k0 = 0; k0 < M; k0 += CK) {
-        sfor<0, CK>([&](auto CI) SI { sfor<0, R>([&](auto RI) SI { cb[CI][RI] = nb[CI][RI]; }); });
-        if (k0 + CK < M) fetch_fwd(nb, k0 + CK);
+        sfor<0, CK>([&](auto CI) SI {
+            cr[CI] = nr[CI];
+            sfor<0, R>([&](auto RI) SI { cb[CI][RI] = nb[CI][RI]; });
+        });
+        if (k0 + CK < M) fetch_fwd(nb, nr, k0 + CK);
         sfor<0, CK>([&](auto CI) SI {
             constexpr int c = CI;
             const int kk = k0 + c;
             if (kk < M) {
-                const double rk = rinv[kk];
+                const double rk = cr[c];
                 const int pl = kk & 63, pr = kk >> 6;
                 double yp = bcast_d(y[0], pl);
                 sfor<1, R>([&](auto RI) SI {
@@ -66,10 +71,11 @@ __device__ __forceinline__ void replay_solve(const double *F, const double *rinv
         });
     }
     // back substitution
-    auto fetch_bwd = [&](double (&buf)[CK][R], int k1) SI {  // steps k1, k1-1, ...
+    auto fetch_bwd = [&](double (&buf)[CK][R], double (&rb)[CK], int k1) SI {  // steps k1, k1-1, ...
         sfor<0, CK>([&](auto CI) SI {
             constexpr int c = CI;
             const int kk = k1 - c;
+            rb[c] = (kk >= 0) ? rinv[kk] : 0.0;
             sfor<0, R>([&](auto RI) SI {
                 constexpr int r = RI;
                 const int q = lane + 64 * r;
@@ -79,15 +85,18 @@ __device__ __forceinline__ void replay_solve(const double *F, const double *rinv
             });
         });
     };
-    fetch_bwd(nb, M - 1);
+    fetch_bwd(nb, nr, M - 1);
     for (int k1 = M - 1; k1 >= 0; k1 -= CK) {
-        sfor<0, CK>([&](auto CI) SI { sfor<0, R>([&](auto RI) SI { cb[CI][RI] = nb[CI][RI]; }); });
-        if (k1 - CK >= 0) fetch_bwd(nb, k1 - CK);
+        sfor<0, CK>([&](auto CI) SI {
+            cr[CI] = nr[CI];
+            sfor<0, R>([&](auto RI) SI { cb[CI][RI] = nb[CI][RI]; });
+        });
+        if (k1 - CK >= 0) fetch_bwd(nb, nr, k1 - CK);
         sfor<0, CK>([&](auto CI) SI {
             constexpr int c = CI;
             const int kk = k1 - c;
             if (kk >= 0) {
-                const double rk = rinv[kk];
+                const double rk = cr[c];
                 const int pl = kk & 63, pr = kk >> 6;
                 double yk = bcast_d(y[0], pl);
                 sfor<1, R>([&](auto RI) SI {
