@@ -545,12 +545,28 @@ __device__ __forceinline__ bool solve_system(SolveSmem<W, R, NCB, B, CM> &sh, co
     return !dead;
 }
 
+// The solver's LDS.  With OPQ the base address is made opaque to the
+// compiler (an offset of zero that it cannot see through): with a constant
+// base it precomputes the per-slot LDS addresses of the largest variant and
+// keeps them all live, which pushes matrix registers to scratch.
+template <class SM, bool OPQ>
+__device__ __forceinline__ SM &solver_smem(unsigned char *raw) {
+    if constexpr (OPQ) {
+        int zero = 0;
+        __asm__ volatile("" : "+v"(zero));
+        return *reinterpret_cast<SM *>(raw + zero);
+    } else {
+        return *reinterpret_cast<SM *>(raw);
+    }
+}
+
 // One workgroup of W waves per stencil (plain path): weights to w, failures
 // counted in status.
-template <int W, int R, int NCB, int B, int WPE>
+template <int W, int R, int NCB, int B, int WPE, bool OPQ = false>
 __global__ void __launch_bounds__(64 * W)
 __attribute__((amdgpu_waves_per_eu(WPE, WPE))) k_solve(SolveArgs A) {
-    __shared__ SolveSmem<W, R, NCB, B> sh;
+    __shared__ __attribute__((aligned(16))) unsigned char sh_raw[sizeof(SolveSmem<W, R, NCB, B>)];
+    SolveSmem<W, R, NCB, B> &sh = solver_smem<SolveSmem<W, R, NCB, B>, OPQ>(sh_raw);
     __shared__ int skip;
     const int64_t j = blockIdx.x;
     const int t = threadIdx.x;
@@ -601,10 +617,11 @@ __attribute__((amdgpu_waves_per_eu(WPE, WPE))) k_solve(SolveArgs A) {
 // One workgroup per stencil: assemble and eliminate, store the factorization
 // (row t of FactorArgs' arrays) instead of solving; fstat[t] = 0, or
 // RBFSL_E_SINGULAR when the system has no usable pivot.
-template <int W, int R, int NCB, int B, int WPE>
+template <int W, int R, int NCB, int B, int WPE, bool OPQ = false>
 __global__ void __launch_bounds__(64 * W)
 __attribute__((amdgpu_waves_per_eu(WPE, WPE))) k_factor(FactorArgs FA) {
-    __shared__ SolveSmem<W, R, NCB, B> sh;
+    __shared__ __attribute__((aligned(16))) unsigned char sh_raw[sizeof(SolveSmem<W, R, NCB, B>)];
+    SolveSmem<W, R, NCB, B> &sh = solver_smem<SolveSmem<W, R, NCB, B>, OPQ>(sh_raw);
     const SolveArgs &A = FA.s;
     const int64_t j = blockIdx.x;
     const int t = threadIdx.x;
@@ -633,15 +650,15 @@ __attribute__((amdgpu_waves_per_eu(WPE, WPE))) k_factor(FactorArgs FA) {
     if (t == 0) FA.fstat[j] = ok ? 0 : RBFSL_E_SINGULAR;
 }
 
-template <int W, int R, int NCB, int B, int WPE>
+template <int W, int R, int NCB, int B, int WPE, bool OPQ = false>
 hipError_t launch_factor_variant(const FactorArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_factor<W, R, NCB, B, WPE>), dim3((unsigned)a.s.count), dim3(64 * W), 0, s, a);
+    hipLaunchKernelGGL((k_factor<W, R, NCB, B, WPE, OPQ>), dim3((unsigned)a.s.count), dim3(64 * W), 0, s, a);
     return hipGetLastError();
 }
 
-template <int W, int R, int NCB, int B, int WPE>
+template <int W, int R, int NCB, int B, int WPE, bool OPQ = false>
 hipError_t launch_solve_variant(const SolveArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_solve<W, R, NCB, B, WPE>), dim3((unsigned)a.count), dim3(64 * W), 0, s, a);
+    hipLaunchKernelGGL((k_solve<W, R, NCB, B, WPE, OPQ>), dim3((unsigned)a.count), dim3(64 * W), 0, s, a);
     return hipGetLastError();
 }
 
