@@ -162,26 +162,35 @@ __device__ __forceinline__ void basis_all(int L, double al, double be, double u,
 }
 
 
+// lane value moved by a DPP control (CTRL, row and bank masks); lanes the
+// control does not write read 0, the identity of an unsigned maximum
 template <int CTRL, int ROWM, int BANKM>
-__device__ __forceinline__ double dpp_d(double v, double ident) {
-    int lo = __builtin_amdgcn_update_dpp(__double2loint(ident), __double2loint(v), CTRL, ROWM, BANKM, false);
-    int hi = __builtin_amdgcn_update_dpp(__double2hiint(ident), __double2hiint(v), CTRL, ROWM, BANKM, false);
-    return __hiloint2double(hi, lo);
+__device__ __forceinline__ unsigned dpp_u(unsigned v) {
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWM, BANKM, false);
 }
 
-// maximum over the wave of values >= -1 (no NaN), returned to every lane:
-// quad swaps, row shifts, row broadcasts (the classic DPP reduction), then
-// lane 63 holds the result
-__device__ __forceinline__ double max_nn(double a, double b) { return (b > a) ? b : a; }
+// maximum over the wave of 32-bit unsigned values, returned to every lane:
+// quad swaps, row shifts, row broadcasts (the classic DPP reduction, each
+// stage one v_max_u32 with a DPP operand), then lane 63 holds the result
+__device__ __forceinline__ unsigned wave_max_u(unsigned v) {
+    v = max(v, dpp_u<0xB1, 0xF, 0xF>(v));   // quad_perm [1,0,3,2]
+    v = max(v, dpp_u<0x4E, 0xF, 0xF>(v));   // quad_perm [2,3,0,1]
+    v = max(v, dpp_u<0x114, 0xF, 0xE>(v));  // row_shr:4
+    v = max(v, dpp_u<0x118, 0xF, 0xC>(v));  // row_shr:8
+    v = max(v, dpp_u<0x142, 0xA, 0xF>(v));  // row_bcast:15
+    v = max(v, dpp_u<0x143, 0xC, 0xF>(v));  // row_bcast:31
+    return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
 
-__device__ __forceinline__ double wave_max_d(double v) {
-    v = fmax(v, dpp_d<0xB1, 0xF, 0xF>(v, -1.0));   // quad_perm [1,0,3,2]
-    v = fmax(v, dpp_d<0x4E, 0xF, 0xF>(v, -1.0));   // quad_perm [2,3,0,1]
-    v = fmax(v, dpp_d<0x114, 0xF, 0xE>(v, -1.0));  // row_shr:4
-    v = fmax(v, dpp_d<0x118, 0xF, 0xC>(v, -1.0));  // row_shr:8
-    v = fmax(v, dpp_d<0x142, 0xA, 0xF>(v, -1.0));  // row_bcast:15
-    v = fmax(v, dpp_d<0x143, 0xC, 0xF>(v, -1.0));  // row_bcast:31
-    return bcast_d(v, 63);
+// maximum over the wave of doubles that are >= +0 and not NaN: for such
+// values the numeric order is the unsigned order of the bit patterns, so the
+// high words are reduced first, then the low words of the lanes that hold the
+// largest high word
+__device__ __forceinline__ double wave_max_nonneg(double v) {
+    const unsigned hi = (unsigned)__double2hiint(v), lo = (unsigned)__double2loint(v);
+    const unsigned H = wave_max_u(hi);
+    const unsigned Lw = wave_max_u(hi == H ? lo : 0u);
+    return __hiloint2double((int)H, (int)Lw);
 }
 
 
@@ -314,13 +323,13 @@ __device__ __forceinline__ bool solve_system(SolveSmem<W, R, NCB, B, CM> &sh, co
             constexpr int c = CI;
             if (c >= cnt || stop) return;
             const int kk = k0 + c;
-            double best = -1.0;
+            double best = 0.0;  // NaN entries never win (v > best is false)
             sfor<0, R>([&](auto RI) SI {
                 constexpr int r = RI;
                 const double v = fabs(a[r][ps0 + c]);
                 if (!used[r] && v > best) best = v;
             });
-            const double m = wave_max_d(best);
+            const double m = wave_max_nonneg(best);
             if (!(m > 0.0)) {
                 if (lane == 0) failk[g & 1] = kk;
                 stop = true;
