@@ -439,7 +439,7 @@ __device__ __forceinline__ bool solve_system(SolveSmem<W, R, NCB, B, CM> &sh, co
             const int cnt = ((kend < fa) ? kend : fa) - k0;
             if (wv > ow) upd(std::integral_constant<int, sb * B>{}, std::integral_constant<int, NC>{}, YES{}, g, cnt);
             else upd(std::integral_constant<int, (sb + 1) * B>{}, std::integral_constant<int, NC>{}, YES{}, g, cnt);
-            dead = (fa != NOFAIL);
+            dead = dead || (fa != NOFAIL);
         }
     });
     if (!LOCK && dead) return false;
