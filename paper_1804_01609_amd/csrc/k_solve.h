@@ -473,18 +473,24 @@ __device__ __forceinline__ bool solve_system(SolveSmem<W, R, NCB, B, CM> &sh, co
 
     // ---- back substitution, chunks of CSB slot-blocks from the right ----
     // slot-blocks [sb1, sb2) of every wave cover columns [sb1*W*B, sb2*W*B);
-    // wave 0 holds the pivots and reciprocals in registers (lane k % 64)
+    // wave 0 holds the pivot rows in registers (lane k % 64, slot k / 64) and,
+    // for each of its rows, the reciprocal of the pivot of the step at which
+    // the row was the pivot row.  Unknown k is z_k = y_p * r_k with p the
+    // pivot row of step k: it is formed in row p's lane and broadcast.  A
+    // row's y is final once its own step is reached, so every unknown is
+    // again y_p * r_k at the end, where wave 0 writes them all at once.
     constexpr int KT = (MCAP + 63) / 64;
     int pivr[KT];
-    double rinvr[KT];
     sfor<0, KT>([&](auto TI) SI {
         constexpr int tt = TI;
         const int kk = lane + 64 * tt;
         pivr[tt] = (kk < M) ? pivb[kk] : 0;
-        rinvr[tt] = (kk < M) ? rinvb[kk] : 0.0;
     });
-    double zr[KT];
-    sfor<0, KT>([&](auto TI) SI { zr[TI] = 0.0; });
+    double rrow[R];
+    sfor<0, R>([&](auto RI) SI {
+        constexpr int r = RI;
+        rrow[r] = (stepof[r] < M) ? rinvb[stepof[r]] : 0.0;
+    });
     double *UB = stage;
     sfor<0, C::NCHUNK>([&](auto CI) SI {
         constexpr int ch = C::NCHUNK - 1 - CI;
@@ -512,28 +518,21 @@ __device__ __forceinline__ bool solve_system(SolveSmem<W, R, NCB, B, CM> &sh, co
                 const int kn = (kk > c0) ? kk - 1 : c0;
                 sfor<0, R>([&](auto RI) SI { un[RI] = UB[(kn - c0) * ROWS + lane + 64 * RI]; });
                 const int kl = kk & 63, kt = kk >> 6;
-                // pivot row and reciprocal of step kk (register slot kt, lane kl)
+                // pivot row of step kk (register slot kt, lane kl)
                 int pk = __builtin_amdgcn_readlane(pivr[0], kl);
-                double rk = bcast_d(rinvr[0], kl);
                 sfor<1, KT>([&](auto TI) SI {
                     constexpr int tt = TI;
                     const int pt = __builtin_amdgcn_readlane(pivr[tt], kl);
-                    const double rt = bcast_d(rinvr[tt], kl);
                     pk = (kt == tt) ? pt : pk;
-                    rk = (kt == tt) ? rt : rk;
                 });
                 const int pl = pk & 63, pr = pk >> 6;
-                double yk = bcast_d(y[0], pl);
+                double ysel = y[0], rsel = rrow[0];
                 sfor<1, R>([&](auto RI) SI {
                     constexpr int r = RI;
-                    const double yr = bcast_d(y[r], pl);
-                    yk = (pr == r) ? yr : yk;
+                    ysel = (pr == r) ? y[r] : ysel;
+                    rsel = (pr == r) ? rrow[r] : rsel;
                 });
-                const double zk = yk * rk;
-                sfor<0, KT>([&](auto TI) SI {
-                    constexpr int tt = TI;
-                    zr[tt] = (kt == tt && lane == kl) ? zk : zr[tt];
-                });
+                const double zk = bcast_d(ysel * rsel, pl);
                 sfor<0, R>([&](auto RI) SI {
                     constexpr int r = RI;
                     const double yn = fma(-u[r], zk, y[r]);
@@ -543,10 +542,9 @@ __device__ __forceinline__ bool solve_system(SolveSmem<W, R, NCB, B, CM> &sh, co
         }
     });
     if (wv == 0) {
-        sfor<0, KT>([&](auto TI) SI {
-            constexpr int tt = TI;
-            const int kk = lane + 64 * tt;
-            if (kk < M) zb[kk] = zr[tt];
+        sfor<0, R>([&](auto RI) SI {
+            constexpr int r = RI;
+            if (stepof[r] < M) zb[stepof[r]] = y[r] * rrow[r];
         });
     }
     __syncthreads();
