@@ -377,26 +377,28 @@ __device__ __forceinline__ bool solve_system(SolveSmem<W, R, NCB, B, CM> &sh, co
         });
     };
     // apply the rank-1 updates of block g's steps, in step order, to this
-    // wave's slots S0 .. NC-1; mark the pivot rows as used and update the
-    // right-hand side.  Row p's entries reach every lane by readlane.
-    auto upd = [&](auto S0C, auto S1C, auto YC, int g, int cnt) SI {
+    // wave's slots S0 .. NC-1 and mark the pivot rows as used.  Row p's
+    // entries reach every lane by readlane.  Only wave 0 carries the
+    // right-hand side (the back substitution is its alone).  The block's
+    // pivot rows are read once (lane c holds step c's), the multipliers one
+    // step ahead.
+    auto upd = [&](auto S0C, auto S1C, int g, int cnt) SI {
         constexpr int S0 = S0C, S1 = S1C;
-        constexpr bool DO_Y = YC;
+        const bool doY = (wv == 0);
         const int k0 = g * B;
         for (int c = 0; c < cnt; ++c) {
             const int kk = k0 + c;
             const int p = pivb[kk];
             const int pl = p & 63, pr = p >> 6;
             double l[R];
+            sfor<0, R>([&](auto RI) SI { l[RI] = lb[g & 1][c][lane + 64 * RI]; });
             sfor<0, R>([&](auto RI) SI {
                 constexpr int r = RI;
                 if (pr == r && lane == pl) { used[r] = true; stepof[r] = kk; }
-                l[r] = lb[g & 1][c][lane + 64 * r];
             });
             sfor<0, R>([&](auto PRI) SI {
                 constexpr int prr = PRI;
                 if (pr == prr) {
-                    const double yp = DO_Y ? bcast_d(y[prr], pl) : 0.0;
                     sfor<S0, S1>([&](auto S) SI {
                         constexpr int sl = S;
                         const double u = bcast_d(a[prr][sl], pl);
@@ -408,7 +410,8 @@ __device__ __forceinline__ bool solve_system(SolveSmem<W, R, NCB, B, CM> &sh, co
                         // otherwise hoist them all and run out of registers)
                         if constexpr ((sl - S0) % 4 == 3) __builtin_amdgcn_sched_barrier(0);
                     });
-                    if constexpr (DO_Y) {
+                    if (doY) {
+                        const double yp = bcast_d(y[prr], pl);
                         sfor<0, R>([&](auto RI) SI {
                             constexpr int r = RI;
                             y[r] = fma(-l[r], yp, y[r]);
@@ -418,7 +421,6 @@ __device__ __forceinline__ bool solve_system(SolveSmem<W, R, NCB, B, CM> &sh, co
             });
         }
     };
-    using YES = std::integral_constant<bool, true>;
     bool dead = false;
     // blocks g = sb * W + ow: the slot-block sb is a compile-time loop, the
     // owner wave ow a runtime loop, so every register slot stays static
@@ -437,8 +439,8 @@ __device__ __forceinline__ bool solve_system(SolveSmem<W, R, NCB, B, CM> &sh, co
             const int fa = failk[g & 1];
             const int kend = (k0 + B < M) ? k0 + B : M;
             const int cnt = ((kend < fa) ? kend : fa) - k0;
-            if (wv > ow) upd(std::integral_constant<int, sb * B>{}, std::integral_constant<int, NC>{}, YES{}, g, cnt);
-            else upd(std::integral_constant<int, (sb + 1) * B>{}, std::integral_constant<int, NC>{}, YES{}, g, cnt);
+            if (wv > ow) upd(std::integral_constant<int, sb * B>{}, std::integral_constant<int, NC>{}, g, cnt);
+            else upd(std::integral_constant<int, (sb + 1) * B>{}, std::integral_constant<int, NC>{}, g, cnt);
             dead = dead || (fa != NOFAIL);
         }
     });
