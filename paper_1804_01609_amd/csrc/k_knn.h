@@ -84,8 +84,33 @@ __device__ __forceinline__ bool knn_wave(KnnSmem<CAP> &sh, const int tid, const 
             int cy = ly + r % nby;
             int cz = lz + r / nby;
             int c = (cz * G + cy) * G + cx;
-            int b = g.cell_start[c], e = g.cell_start[c + 1];
-            for (int p = b; p < e; ++p) {
+            const int b = g.cell_start[c], e = g.cell_start[c + 1];
+            // four nodes per round: their loads are in flight together
+            int p = b;
+            for (; p + 4 <= e; p += 4) {
+                double x[4], y[4], z[4];
+                int id[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    x[u] = g.sx[p + u];
+                    y[u] = g.sy[p + u];
+                    z[u] = g.sz[p + u];
+                    id[u] = g.perm[p + u];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    double d0 = x[u] - q0, d1 = y[u] - q1, dd = z[u] - q2;
+                    double dist = (d0 * d0 + d1 * d1) + dd * dd;
+                    if (dist < Rt2) {
+                        int slot = atomicAdd(&sh.cnt, 1);
+                        if (slot < CAP) {
+                            kd[slot] = dist;
+                            ki[slot] = id[u];
+                        }
+                    }
+                }
+            }
+            for (; p < e; ++p) {
                 double d0 = g.sx[p] - q0, d1 = g.sy[p] - q1, dd = g.sz[p] - q2;
                 double dist = (d0 * d0 + d1 * d1) + dd * dd;
                 if (dist < Rt2) {
@@ -114,6 +139,25 @@ __device__ __forceinline__ bool knn_wave(KnnSmem<CAP> &sh, const int tid, const 
         }
     }
     if (!ok) return false;
+    if (n == 1) {
+        // the nearest node alone: the smallest key, no sort
+        if (lane == 0) {
+            double bd = kd[0];
+            int bi = ki[0];
+            for (int t = 1; t < F; ++t) {
+                const double d = kd[t];
+                const int i = ki[t];
+                if (d < bd || (d == bd && i < bi)) {
+                    bd = d;
+                    bi = i;
+                }
+            }
+            kd[0] = bd;
+            ki[0] = bi;
+        }
+        knn_sync<NWV>();
+        return true;
+    }
     int P = 64;
     while (P < F) P <<= 1;
     for (int t = F + lane; t < P; t += NT) {

@@ -4,16 +4,19 @@
 
 namespace rbfsl {
 
+constexpr int KNN_SMALL_N = 256;
+
+template <int CAP>
 __global__ void __launch_bounds__(64) k_knn(GridView g, const double *__restrict__ qx,
                                             const double *__restrict__ qy,
                                             const double *__restrict__ qz, int n, double R_init,
                                             int32_t *__restrict__ idx, double *__restrict__ d2out,
                                             double *__restrict__ s2out, int *status, int64_t step) {
-    __shared__ KnnSmem<KNN_CAP> sh;
+    __shared__ KnnSmem<CAP> sh;
     if (status[ST_FAILSTEP] < step) return;
     const int64_t q = blockIdx.x;
     const int lane = threadIdx.x;
-    if (!knn_wave<KNN_CAP>(sh, lane, g, qx[q], qy[q], qz[q], n, R_init)) {
+    if (!knn_wave<CAP>(sh, lane, g, qx[q], qy[q], qz[q], n, R_init)) {
         if (lane == 0) {
             atomicAdd(&status[ST_SEARCH], 1);
             atomicMin(&status[ST_FAILSTEP], (int)step);
@@ -38,8 +41,19 @@ hipError_t launch_knn(const Grid &g, int64_t N, const double *qx, const double *
                       int *status, int64_t step, hipStream_t s) {
     if (Q <= 0) return hipSuccess;
     const GridView gv{g.G, g.invh, g.cell_start, g.sx, g.sy, g.sz, g.perm};
-    hipLaunchKernelGGL(k_knn, dim3((unsigned)Q), dim3(64), 0, s, gv, qx, qy, qz, n,
-                       knn_first_radius(n, N), idx, d2, s2, status, step);
+    // the first radius keeps about 1.4 n nodes: for small n a quarter- or
+    // half-size candidate store suffices (the radius adapts when it does not),
+    // and its smaller LDS footprint lets more searches share a compute unit
+    const double R0 = knn_first_radius(n, N);
+    if (n <= KNN_SMALL_N / 2)
+        hipLaunchKernelGGL(k_knn<KNN_CAP / 4>, dim3((unsigned)Q), dim3(64), 0, s, gv, qx, qy, qz, n, R0, idx, d2,
+                           s2, status, step);
+    else if (n <= KNN_SMALL_N)
+        hipLaunchKernelGGL(k_knn<KNN_CAP / 2>, dim3((unsigned)Q), dim3(64), 0, s, gv, qx, qy, qz, n, R0, idx, d2,
+                           s2, status, step);
+    else
+        hipLaunchKernelGGL(k_knn<KNN_CAP>, dim3((unsigned)Q), dim3(64), 0, s, gv, qx, qy, qz, n, R0, idx, d2,
+                           s2, status, step);
     return hipGetLastError();
 }
 
