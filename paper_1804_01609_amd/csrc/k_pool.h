@@ -59,6 +59,25 @@ __device__ __forceinline__ int64_t uniform64(int64_t v) {
     return (int64_t)(((uint64_t)(unsigned)hi << 32) | (unsigned)lo);
 }
 
+// sum_a w[a] q[a] as one fma chain in stencil order, both operands in LDS;
+// the loads of eight terms are issued together ahead of their fmas
+__device__ __forceinline__ double lds_dot_chain(const double *w, const double *q, const int n) {
+    double acc = 0.0;
+    int a = 0;
+    for (; a + 8 <= n; a += 8) {
+        double wv[8], qv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            wv[u] = w[a + u];
+            qv[u] = q[a + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = fma(wv[u], qv[u], acc);
+    }
+    for (; a < n; ++a) acc = fma(w[a], q[a], acc);
+    return acc;
+}
+
 struct ItemInfo {
     int64_t j0, step;
     int slot, var, cnt, cur, valid, skip;
@@ -129,10 +148,7 @@ __device__ __forceinline__ void pool_item(const PoolArgs &P, const ItemInfo &I, 
         double *qout = r.q[1 - I.cur];
         if (pre) {
             for (int tr = lane; tr < r.ntr; tr += 64) {
-                const double *qa = S.qp + tr * n;
-                double acc = 0.0;
-                for (int a = 0; a < n; ++a) acc = fma(zb[a], qa[a], acc);
-                qout[(int64_t)tr * N + j] = acc;
+                qout[(int64_t)tr * N + j] = lds_dot_chain(zb, S.qp + tr * n, n);
             }
             return;
         }
@@ -150,10 +166,7 @@ __device__ __forceinline__ void pool_item(const PoolArgs &P, const ItemInfo &I, 
             }
             wave_lds_sync();
             if (lane < tc) {
-                const double *qa = qg + lane * n;
-                double acc = 0.0;
-                for (int a = 0; a < n; ++a) acc = fma(zb[a], qa[a], acc);
-                qout[(int64_t)(t0 + lane) * N + j] = acc;
+                qout[(int64_t)(t0 + lane) * N + j] = lds_dot_chain(zb, qg + lane * n, n);
             }
             wave_lds_sync();
         }
