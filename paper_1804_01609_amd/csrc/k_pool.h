@@ -183,38 +183,77 @@ __device__ __forceinline__ void pool_dispatch(const int var, const PoolArgs &P, 
     }
 }
 
-// Claims items until the queue is empty.  Thread 0 claims and decodes; the
-// item record is double-buffered so one barrier per item suffices.
+// Thread 0's claim state, kept in LDS (not in registers, which the solver
+// needs): the claimed but unprocessed items, and the last decoded segment
+// with everything about it that is fixed during the step.
+struct ClaimCache {
+    int64_t nxt, end;    // claimed items not yet processed: [nxt, end)
+    int64_t s_lo, s_hi;  // item range of the cached segment
+    int64_t nitems, item0, N, step, nsteps;
+    const int *status;
+    int slot, var, G, cur;
+};
+
+// Claims items until the queue is empty.  Thread 0 claims POOL_CLAIM items
+// per atomic and decodes them, searching the segment table only when an
+// item leaves the cached segment; the item record is double-buffered so one
+// barrier per item suffices.
+constexpr int POOL_CLAIM = 2;
 template <int NW, int WPE, class... V>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 k_pool(PoolArgs P) {
     __shared__ __attribute__((aligned(16))) unsigned char smem[pool_smem_max<NW, V...>()];
     __shared__ ItemInfo info[2];
+    __shared__ ClaimCache cc;
     const int t = threadIdx.x;
     PoolQueue *Q = P.queue;
+    if (t == 0) {
+        cc.nxt = cc.end = 0;
+        cc.s_lo = cc.s_hi = 0;
+        cc.nitems = Q->nitems;
+    }
     for (int it = 0;; ++it) {
         ItemInfo &I = info[it & 1];
         if (t == 0) {
-            const int64_t item = (int64_t)atomicAdd(&Q->next, 1ull);
-            I.valid = item < Q->nitems;
+            if (cc.nxt >= cc.end) {
+                const int64_t b = (int64_t)atomicAdd(&Q->next, (unsigned long long)POOL_CLAIM);
+                cc.nxt = b;
+                cc.end = b + POOL_CLAIM;
+            }
+            const int64_t item = cc.nxt++;
+            I.valid = item < cc.nitems;
             if (I.valid) {
-                int lo = 0, hi = Q->nseg - 1;  // last segment with item0 <= item
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (Q->seg[mid].item0 <= item) lo = mid;
-                    else hi = mid - 1;
+                if (!(item >= cc.s_lo && item < cc.s_hi)) {
+                    const int nseg = Q->nseg;
+                    int lo = 0, hi = nseg - 1;  // last segment with item0 <= item
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (Q->seg[mid].item0 <= item) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    const PoolSeg &sg = Q->seg[lo];
+                    cc.s_lo = sg.item0;
+                    cc.s_hi = (lo + 1 < nseg) ? Q->seg[lo + 1].item0 : cc.nitems;
+                    cc.item0 = sg.item0;
+                    cc.N = sg.N;
+                    cc.G = sg.G;
+                    cc.slot = sg.slot;
+                    cc.var = sg.var;
+                    cc.step = P.state[sg.slot].step;
+                    cc.cur = P.state[sg.slot].cur;
+                    const PoolRunDev &r = P.runs[sg.slot];
+                    cc.nsteps = r.nsteps;
+                    cc.status = r.status;
                 }
-                const PoolSeg &sg = Q->seg[lo];
-                const int64_t j0 = (item - sg.item0) * sg.G;
-                I.slot = sg.slot;
-                I.var = sg.var;
+                const int64_t j0 = (item - cc.item0) * cc.G;
+                I.slot = cc.slot;
+                I.var = cc.var;
                 I.j0 = j0;
-                I.cnt = (int)((sg.N - j0 < sg.G) ? sg.N - j0 : sg.G);
-                I.step = P.state[sg.slot].step;
-                I.cur = P.state[sg.slot].cur;
-                const PoolRunDev &r = P.runs[sg.slot];
+                I.cnt = (int)((cc.N - j0 < cc.G) ? cc.N - j0 : cc.G);
+                I.step = cc.step;
+                I.cur = cc.cur;
                 // finished, or failed at this or an earlier step
-                I.skip = (I.step >= r.nsteps) || (r.status[ST_FAILSTEP] <= I.step);
+                I.skip = (cc.step >= cc.nsteps) || (cc.status[ST_FAILSTEP] <= cc.step);
             }
         }
         __syncthreads();

@@ -18,15 +18,22 @@ __global__ void __launch_bounds__(64) k_pool_search(PoolArgs P) {
     const PoolQueue *Q = P.queue;
     const int64_t nitems = Q->nitems;
     const int nseg = Q->nseg;
+    int lo = 0;
+    int64_t s_lo = 0, s_hi = 0;  // item range of segment lo, searched only when an item leaves it
     for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
-        int lo = 0, hi = nseg - 1;  // last segment with item0 <= item
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (Q->seg[mid].item0 <= item) lo = mid;
-            else hi = mid - 1;
+        if (!(item >= s_lo && item < s_hi)) {
+            int l = 0, hi = nseg - 1;  // last segment with item0 <= item
+            while (l < hi) {
+                const int mid = (l + hi + 1) >> 1;
+                if (Q->seg[mid].item0 <= item) l = mid;
+                else hi = mid - 1;
+            }
+            lo = l;
+            s_lo = Q->seg[lo].item0;
+            s_hi = (lo + 1 < nseg) ? Q->seg[lo + 1].item0 : nitems;
         }
         const int slot = __builtin_amdgcn_readfirstlane(Q->seg[lo].slot);
-        const int64_t j = item - Q->seg[lo].item0;
+        const int64_t j = item - s_lo;
         const PoolRunDev &r = P.runs[slot];
         const int64_t step = P.state[slot].step;
         if (step >= r.nsteps || r.status[ST_FAILSTEP] <= step) continue;
