@@ -24,7 +24,23 @@ __global__ void __launch_bounds__(256) k_apply(const double *__restrict__ w,
     const int32_t *Sj = S + row * n;
     const double *q = qin + (int64_t)t * N;
     double acc = 0.0;
-    for (int a = 0; a < n; ++a) acc = fma(wj[a], q[Sj[a]], acc);
+    int a = 0;
+    // eight terms per round: their index, weight and value loads are in
+    // flight together ahead of the fmas (the chain order is unchanged)
+    for (; a + 8 <= n; a += 8) {
+        int32_t s8[8];
+        double w8[8], q8[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            s8[u] = Sj[a + u];
+            w8[u] = wj[a + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) q8[u] = q[s8[u]];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = fma(w8[u], q8[u], acc);
+    }
+    for (; a < n; ++a) acc = fma(wj[a], q[Sj[a]], acc);
     qout[(int64_t)t * N + j] = acc;
 }
 
