@@ -5,6 +5,7 @@
 namespace rbfsl {
 
 hipError_t solve_m48(const SolveArgs &a, hipStream_t s);
+hipError_t solve_m48_wide(const SolveArgs &a, hipStream_t s);
 hipError_t solve_m64(const SolveArgs &a, hipStream_t s);
 hipError_t solve_m81(const SolveArgs &a, hipStream_t s);
 hipError_t solve_m96(const SolveArgs &a, hipStream_t s);
@@ -46,10 +47,16 @@ int solve_variant_capacity(int M) {
     return v ? v->mcap : 0;
 }
 
+// a launch of at most this many systems of the smallest capacity uses four
+// waves per system: with one wave per system, 1,024 systems occupy one wave
+// slot of each SIMD and every system's elimination runs serially in its wave
+constexpr int64_t SMALL_LAUNCH = 1024;
+
 hipError_t launch_solve(const SolveArgs &a, hipStream_t s) {
     if (a.count <= 0) return hipSuccess;
     const Variant *v = pick(a.n + (a.L + 1) * (a.L + 1));
     if (!v) return hipErrorInvalidValue;
+    if (v->mcap == 48 && a.count <= SMALL_LAUNCH) return solve_m48_wide(a, s);
     return v->fn(a, s);
 }
 
