@@ -379,9 +379,7 @@ __device__ __forceinline__ bool solve_system(SolveSmem<W, R, NCB, B, CM> &sh, co
     // apply the rank-1 updates of block g's steps, in step order, to this
     // wave's slots S0 .. NC-1 and mark the pivot rows as used.  Row p's
     // entries reach every lane by readlane.  Only wave 0 carries the
-    // right-hand side (the back substitution is its alone).  The block's
-    // pivot rows are read once (lane c holds step c's), the multipliers one
-    // step ahead.
+    // right-hand side (the back substitution is its alone).
     auto upd = [&](auto S0C, auto S1C, int g, int cnt) SI {
         constexpr int S0 = S0C, S1 = S1C;
         const bool doY = (wv == 0);
