@@ -25,7 +25,7 @@ __global__ void __launch_bounds__(256) k_apply(const double *__restrict__ w,
     const double *q = qin + (int64_t)t * N;
     double acc = 0.0;
     int a = 0;
-    // eight terms per round: their index, weight and value loads are in
+    // eight terms per iteration: their index, weight and value loads are in
     // flight together ahead of the fmas (the chain order is unchanged)
     for (; a + 8 <= n; a += 8) {
         int32_t s8[8];

@@ -85,7 +85,7 @@ __device__ __forceinline__ bool knn_wave(KnnSmem<CAP> &sh, const int tid, const 
             int cz = lz + r / nby;
             int c = (cz * G + cy) * G + cx;
             const int b = g.cell_start[c], e = g.cell_start[c + 1];
-            // four nodes per round: their loads are in flight together
+            // four nodes per iteration: their loads are in flight together
             int p = b;
             for (; p + 4 <= e; p += 4) {
                 double x[4], y[4], z[4];
