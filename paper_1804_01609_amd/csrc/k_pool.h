@@ -5,8 +5,8 @@
 // node of each run; the search does not depend on q and runs at its own,
 // higher occupancy).
 //
-// Workgroups of NW waves claim items from the family's queue with one atomic
-// each.  An item is G consecutive nodes of one run, G = NW / W for a solver
+// Workgroups of NW waves claim items from the family's queue, two per atomic
+// (k_pool below).  An item is G consecutive nodes of one run, G = NW / W for a solver
 // variant with W waves per stencil: the G stencil groups of the workgroup
 // work side by side, each on its own node.  Per node: the q^m values of the
 // stencil are fetched into LDS (their latency hides behind the assembly),
