@@ -96,7 +96,10 @@ typedef struct {
     double t0;            /* time of step 0                                               */
 } rbfsl_params;
 
-/* Create a transport context.
+/* Create a transport context: the inputs of Algorithm 1 (Section 3) -- the
+ * node set X on the sphere, the velocity u (velocity_id, vel), the time step
+ * dt and start t0 -- and the local method's stencil size n with its harmonic
+ * degree L and PHS order k (Sections 2.2 and 2.4).
  * nodes_xyz: N x 3 row-major (x, y, z) of nodes on the unit sphere (copied).
  * Builds the spatial hash of the nodes (and, in stencil_mode 1, every node's
  * stencil) on the device.  (n + (L+1)^2) must not exceed rbfsl_max_system().
@@ -134,19 +137,26 @@ int rbfsl_pu_info(const rbfsl_ctx *ctx, int64_t *npatch, int32_t *ncap, int32_t 
  * first count entries of each row are the patch's nodes). */
 int rbfsl_debug_patches(rbfsl_ctx *ctx, int32_t *counts, int32_t *idx);
 
-/* Set q^m (n_tracers x N row-major, copied).  Does not change the step index. */
+/* Set q^m, the field values at the nodes (Algorithm 1's q^0 = q(X, 0) when
+ * called before the first step): n_tracers x N row-major, copied.  Does not
+ * change the step index. */
 int rbfsl_set_q(rbfsl_ctx *ctx, const double *q, int on_device);
 
-/* One step q^m -> q^{m+1}.  Synchronises and commits only if every stencil
+/* One pass of Algorithm 1's loop, q^m -> q^{m+1}: trace every node back over
+ * [t_m, t_{m+1}] (eq. sl_ode, Section 3.2), interpolate q^m at the departure
+ * points with the local interpolant (eq. rbf_poly, Section 3.3.2) and assign
+ * the values to the nodes.  Synchronises and commits only if every stencil
  * solved: on RBFSL_E_SINGULAR / _NONFINITE / _SEARCH the state stays at m. */
 int rbfsl_step(rbfsl_ctx *ctx);
 
-/* nsteps steps, enqueued without host synchronisation between them; one
- * synchronisation at the end.  If step f fails, later steps do nothing and the
- * state is left at step f (q^f), with the failure code returned. */
+/* nsteps passes of Algorithm 1's loop (each as rbfsl_step), enqueued without
+ * host synchronisation between them; one synchronisation at the end.  If step
+ * f fails, later steps do nothing and the state is left at step f (q^f), with
+ * the failure code returned. */
 int rbfsl_run(rbfsl_ctx *ctx, int64_t nsteps);
 
-/* Copy q^m out (n_tracers x N).  Synchronises. */
+/* Copy q^m, Algorithm 1's state after m steps, out (n_tracers x N).
+ * Synchronises. */
 int rbfsl_get_q(rbfsl_ctx *ctx, double *out, int on_device);
 
 /* Current step index m and time t0 + m dt. */
@@ -172,6 +182,12 @@ int rbfsl_phase_times(rbfsl_ctx *ctx, double *ms, int64_t *steps);
 int rbfsl_debug_departure(rbfsl_ctx *ctx, double *xi);
 int rbfsl_debug_stencils(rbfsl_ctx *ctx, int32_t *idx);
 int rbfsl_debug_weights(rbfsl_ctx *ctx, double *w);
+/* The same taps for J selected nodes jl[0..J) (host int64 indices in [0, N)),
+ * gathered on the device: xi J x 3, idx J x n, w J x n (any may be NULL;
+ * idx and w are RBFSL_E_INVAL for RBF-PU contexts).  An index outside [0, N)
+ * is RBFSL_E_INVAL and nothing is written. */
+int rbfsl_debug_sample(rbfsl_ctx *ctx, const int64_t *jl, int64_t J, double *xi, int32_t *idx,
+                       double *w);
 
 /* Stateless exact neighbour search through the spatial hash: for each of Q
  * query points (Q x 3), the n nodes with the smallest keys (d^2, index),
@@ -191,6 +207,11 @@ int rbfsl_weights(const double *nodes_xyz, int64_t N, const int32_t *idx, const 
 
 /* Largest supported system size n + (L+1)^2. */
 int rbfsl_max_system(void);
+
+/* sha256 (hex) of the sources this library was built from, as the build
+ * computes it; a binding compares it with the sources next to it to refuse a
+ * stale library.  Static string. */
+const char *rbfsl_source_hash(void);
 
 const char *rbfsl_strerror(int code);
 /* Message of the last failure on this context (owned by the context, valid

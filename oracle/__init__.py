@@ -18,7 +18,11 @@ ORC_OK, ORC_SINGULAR, ORC_NONFINITE, ORC_INVAL = 0, 1, 2, 3
 VEL_ZERO, VEL_SOLID, VEL_DEFORM, VEL_NL2010 = 0, 1, 2, 3
 RK4, RK5F = 0, 1
 
-CFLAGS = ["-O2", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off", "-mfma", "-fopenmp"]
+# -O3 with the x86-64-v3 instruction set (AVX2 + FMA) rather than
+# -march=native: the library is built on one host and may be loaded on another
+# (the GPU machine's), and every x86-64 server of the last decade has v3.
+# Vector code does not change any result: no contraction, no reassociation.
+CFLAGS = ["-O3", "-march=x86-64-v3", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp"]
 
 
 def build(force=True):

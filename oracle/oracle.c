@@ -14,7 +14,8 @@
  *      projecting every stage point and the result orthogonally back onto
  *      the unit sphere;
  *   2. stencils: the n nearest nodes of each departure point, by brute force
- *      (all N keys sorted);  the kd-tree of Section 2.2 only accelerates this;
+ *      (all N keys formed, the n smallest kept);  the kd-tree of Section 2.2
+ *      only accelerates this;
  *   3. the augmented local interpolant (eq. rbf_poly) with PHS phi = r^(2k+1)
  *      (Section 2.4) and the degree-L spherical-harmonic space, whose moment
  *      conditions give the saddle-point system (eq. rbf_poly_linsys);
@@ -309,16 +310,50 @@ static double dist2(const double *x, const double *q) {
     return (d0 * d0 + d1 * d1) + d2 * d2;
 }
 
-static void knn_one(int64_t N, const double *nodes, const double *q, int n, key_t_ *scratch,
-                    int32_t *idx, double *d2) {
-    for (int64_t i = 0; i < N; ++i) {
-        scratch[i].d2 = dist2(nodes + 3 * i, q);
-        scratch[i].i = (int32_t)i;
+static int key_less(const key_t_ *a, const key_t_ *b) { return key_cmp(a, b) < 0; }
+
+/* restore the max-heap order of h[0..cnt) below position r (the largest key
+ * at the root) */
+static void heap_sift_down(key_t_ *h, int cnt, int r) {
+    for (;;) {
+        int c = 2 * r + 1;
+        if (c >= cnt) return;
+        if (c + 1 < cnt && key_less(&h[c], &h[c + 1])) c = c + 1;
+        if (!key_less(&h[r], &h[c])) return;
+        key_t_ t = h[r]; h[r] = h[c]; h[c] = t;
+        r = c;
     }
-    qsort(scratch, (size_t)N, sizeof(key_t_), key_cmp);
+}
+
+/* The n smallest of all N keys (d2, i), in ascending key order.  Brute force:
+ * every key is formed; a max-heap keeps the n smallest seen so far (a key
+ * enters when it is smaller than the largest kept one), and the kept keys are
+ * sorted at the end.  The keys are all distinct (distinct i), so the result
+ * is the first n entries of the fully sorted key list. */
+static void knn_one(int64_t N, const double *nodes, const double *q, int n, key_t_ *heap,
+                    int32_t *idx, double *d2) {
+    int cnt = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        key_t_ k;
+        k.d2 = dist2(nodes + 3 * i, q);
+        k.i = (int32_t)i;
+        if (cnt < n) {
+            /* grow the heap: put k last and move it up to its place */
+            int c = cnt++;
+            heap[c] = k;
+            while (c > 0 && key_less(&heap[(c - 1) / 2], &heap[c])) {
+                key_t_ t = heap[c]; heap[c] = heap[(c - 1) / 2]; heap[(c - 1) / 2] = t;
+                c = (c - 1) / 2;
+            }
+        } else if (key_less(&k, &heap[0])) {
+            heap[0] = k;
+            heap_sift_down(heap, cnt, 0);
+        }
+    }
+    qsort(heap, (size_t)cnt, sizeof(key_t_), key_cmp);
     for (int a = 0; a < n; ++a) {
-        idx[a] = scratch[a].i;
-        if (d2) d2[a] = scratch[a].d2;
+        idx[a] = heap[a].i;
+        if (d2) d2[a] = heap[a].d2;
     }
 }
 

@@ -12,7 +12,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librbfsl.so")
+# RBFSL_LIB_PATH selects another build of the same sources (the tests load a
+# host-sanitized build this way)
+LIB_PATH = os.environ.get("RBFSL_LIB_PATH") or os.path.join(_HERE, "librbfsl.so")
 
 RBFSL_OK = 0
 RBFSL_E_INVAL = -1
@@ -31,6 +33,7 @@ RK4, RK5_FEHLBERG = 0, 1
 EXPORTS = [
     "rbfsl_create", "rbfsl_set_q", "rbfsl_step", "rbfsl_run", "rbfsl_get_q", "rbfsl_get_state",
     "rbfsl_get_failures", "rbfsl_profile", "rbfsl_phase_times", "rbfsl_debug_departure", "rbfsl_debug_stencils", "rbfsl_debug_weights",
+    "rbfsl_debug_sample", "rbfsl_source_hash",
     "rbfsl_knn", "rbfsl_weights", "rbfsl_max_system", "rbfsl_strerror", "rbfsl_last_error",
     "rbfsl_destroy", "rbfsl_create_pu", "rbfsl_pu_info", "rbfsl_debug_patches",
     "rbfsl_pool_create", "rbfsl_pool_run_bytes", "rbfsl_pool_add", "rbfsl_pool_step", "rbfsl_pool_run_info",
@@ -94,6 +97,12 @@ def lib():
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_1804_01609_amd.build` (hipcc, gfx950)")
         L = ctypes.CDLL(LIB_PATH)
+        L.rbfsl_source_hash.restype = ctypes.c_char_p
+        from . import build as _build
+        built, here = L.rbfsl_source_hash().decode(), _build.source_hash()
+        if built != here:
+            raise RuntimeError(f"{LIB_PATH} was built from other sources (hash {built[:12]}, sources "
+                               f"{here[:12]}): rebuild it with `python -m paper_1804_01609_amd.build`")
         i64, i32 = ctypes.c_int64, ctypes.c_int32
         L.rbfsl_create.argtypes = [_P, i64, ctypes.c_int, ctypes.POINTER(Params), _P, ctypes.POINTER(_P)]
         L.rbfsl_set_q.argtypes = [_P, _P, ctypes.c_int]
@@ -107,6 +116,7 @@ def lib():
         L.rbfsl_debug_departure.argtypes = [_P, _P]
         L.rbfsl_debug_stencils.argtypes = [_P, _P]
         L.rbfsl_debug_weights.argtypes = [_P, _P]
+        L.rbfsl_debug_sample.argtypes = [_P, _P, i64, _P, _P, _P]
         L.rbfsl_create_pu.argtypes = [_P, i64, ctypes.c_int, _P, i64, ctypes.c_double, ctypes.POINTER(Params), _P,
                                       ctypes.POINTER(_P)]
         L.rbfsl_pu_info.argtypes = [_P, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32),
@@ -291,6 +301,17 @@ class Transport:
         w = np.zeros((self.N, self.params.n))
         _check(lib().rbfsl_debug_weights(self._ctx, w.ctypes.data_as(_P)), self._ctx)
         return w
+
+    def sample(self, jl):
+        """Departure points, stencils and weights of the last step at nodes jl."""
+        jl = np.ascontiguousarray(jl, dtype=np.int64)
+        J = jl.shape[0]
+        xi = np.zeros((J, 3))
+        S = np.zeros((J, self.params.n), dtype=np.int32)
+        w = np.zeros((J, self.params.n))
+        _check(lib().rbfsl_debug_sample(self._ctx, jl.ctypes.data_as(_P), J, xi.ctypes.data_as(_P),
+                                        S.ctypes.data_as(_P), w.ctypes.data_as(_P)), self._ctx)
+        return xi, S, w
 
 
 class PuTransport(Transport):

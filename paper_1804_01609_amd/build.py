@@ -4,6 +4,7 @@ Usage: python -m paper_1804_01609_amd.build   (or call build()).
 Objects go to _build/ at the repository root; the library lands next to this
 file so that it ships with the source tree.
 """
+import hashlib
 import os
 import subprocess
 import sys
@@ -35,13 +36,29 @@ FLAGS = [
 ]
 
 
+def source_hash():
+    """sha256 over every file the library is built from (kernels, host code,
+    the C header and this build script, which holds the flags), in name
+    order; the library embeds it and the binding refuses a library whose hash
+    differs from the sources beside it."""
+    files = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".h")))
+    h = hashlib.sha256()
+    for name, path in [(f, os.path.join(CSRC, f)) for f in files] + [
+            ("rbfsl.h", os.path.join(INCLUDE, "rbfsl.h")), ("build.py", os.path.abspath(__file__))]:
+        with open(path, "rb") as fh:
+            data = fh.read()
+        h.update(name.encode() + b"\0" + str(len(data)).encode() + b"\0" + data)
+    return h.hexdigest()
+
+
 def build(verbose=False, jobs=8):
     os.makedirs(BUILD, exist_ok=True)
     objs, procs = [], []
+    shash = source_hash()
     for src in SOURCES:
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
         objs.append(obj)
-        cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC, *FLAGS, f'-DRBFSL_SOURCE_HASH="{shash}"', "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
@@ -53,6 +70,55 @@ def build(verbose=False, jobs=8):
     subprocess.check_call([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp])
     os.replace(tmp, LIB)
     return LIB
+
+
+# host units of the library: parameter validation, buffer ownership, the pool's
+# arena and queues, the serve loop
+HOST_UNITS = ["api.hip", "pool_api.hip"]
+ASAN_LIB = os.path.join(BUILD, "asan", "librbfsl_asan.so")
+
+
+def build_sanitized(verbose=False):
+    """librbfsl with AddressSanitizer and UndefinedBehaviorSanitizer in the
+    host code of HOST_UNITS (GPU code is built as usual; the sanitizers apply
+    to the host pass only).  The other objects come from a regular build().
+    For CPU tests of the host logic; load it with the compiler's ASan runtime
+    preloaded."""
+    objs = [os.path.join(BUILD, s.replace(".hip", ".o")) for s in SOURCES]
+    if not all(os.path.exists(o) for o in objs):
+        build(verbose=verbose)
+    out = os.path.join(BUILD, "asan")
+    os.makedirs(out, exist_ok=True)
+    shash = source_hash()
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=all"]
+    procs, repl = [], {}
+    for src in HOST_UNITS:
+        obj = os.path.join(out, src.replace(".hip", ".o"))
+        repl[os.path.join(BUILD, src.replace(".hip", ".o"))] = obj
+        cmd = [HIPCC, *FLAGS, *san, f'-DRBFSL_SOURCE_HASH="{shash}"', "-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+    for p in procs:
+        _wait(p)
+    objs = [repl.get(o, o) for o in objs]
+    rt = asan_runtime()
+    subprocess.check_call([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-Xarch_host", "-fsanitize=address",
+                           "-Xarch_host", "-fsanitize=undefined", "-shared-libsan",
+                           f"-Wl,-rpath,{os.path.dirname(rt)}", *objs, "-o", ASAN_LIB])
+    return ASAN_LIB
+
+
+def asan_runtime():
+    """The compiler's shared AddressSanitizer runtime (to preload)."""
+    out = subprocess.check_output([os.path.join(os.path.dirname(HIPCC), "..", "llvm", "bin", "clang"),
+                                   "--print-file-name=libclang_rt.asan-x86_64.so"]).decode().strip()
+    if not os.path.isabs(out):
+        import glob
+        hits = glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so")
+        out = hits[0] if hits else out
+    return out
 
 
 def _wait(item):

@@ -157,6 +157,26 @@ __global__ void k_gather_rows(const int32_t *S, const int32_t *cidx, int64_t N, 
     out[i] = S[(int64_t)cidx[j] * n + a];
 }
 
+// rows jl[0..J) of the last step's departure points, stencils and weights
+// (stencils of node K = cidx[j] in the centre-point mode)
+__global__ void k_gather_sample(const int64_t *jl, int64_t J, const double *ex, const double *ey,
+                                const double *ez, const int32_t *S, const int32_t *cidx, const double *w,
+                                int n, double *xi, int32_t *Sout, double *wout) {
+    const int64_t t = (int64_t)blockIdx.x;
+    if (t >= J) return;
+    const int64_t j = jl[t];
+    if (threadIdx.x == 0 && xi) {
+        xi[3 * t] = ex[j];
+        xi[3 * t + 1] = ey[j];
+        xi[3 * t + 2] = ez[j];
+    }
+    const int64_t row = cidx ? (int64_t)cidx[j] : j;
+    for (int a = threadIdx.x; a < n; a += blockDim.x) {
+        if (Sout) Sout[t * n + a] = S[row * n + a];
+        if (wout) wout[t * n + a] = w[j * n + a];
+    }
+}
+
 // upload an N x 3 AoS array (host or device) as SoA device arrays
 hipError_t upload_points(const double *xyz, int64_t N, int on_device, double *x, double *y,
                          double *z, hipStream_t s) {
@@ -729,6 +749,43 @@ int rbfsl_debug_weights(rbfsl_ctx *c, double *w) {
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return RBFSL_OK;
 }
+
+int rbfsl_debug_sample(rbfsl_ctx *c, const int64_t *jl, int64_t J, double *xi, int32_t *idx, double *w) {
+    if (!c || J < 0 || (J > 0 && !jl)) return RBFSL_E_INVAL;
+    if ((idx || w) && c->mode == RBFSL_STENCIL_PU) return RBFSL_E_INVAL;
+    if (!c->ran) return fail(c, RBFSL_E_STATE, "no step has run");
+    for (int64_t t = 0; t < J; ++t)
+        if (jl[t] < 0 || jl[t] >= c->N) return fail(c, RBFSL_E_INVAL, "node index %lld out of range", (long long)jl[t]);
+    if (J == 0) return RBFSL_OK;
+    const size_t d = sizeof(double), nn = (size_t)c->n;
+    int64_t *djl = nullptr;
+    double *dxi = nullptr, *dw = nullptr;
+    int32_t *dS = nullptr;
+    hipError_t e = hipMalloc(&djl, sizeof(int64_t) * J);
+    if (e == hipSuccess) e = hipMalloc(&dxi, d * 3 * J);
+    if (e == hipSuccess && idx) e = hipMalloc(&dS, sizeof(int32_t) * J * nn);
+    if (e == hipSuccess && w) e = hipMalloc(&dw, d * J * nn);
+    if (e == hipSuccess) e = hipMemcpyAsync(djl, jl, sizeof(int64_t) * J, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_gather_sample, dim3((unsigned)J), dim3(64), 0, c->stream, djl, J, c->ex, c->ey,
+                           c->ez, c->S, c->mode == 1 ? c->cidx : nullptr, c->w, c->n, dxi, dS, dw);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && xi) e = hipMemcpyAsync(xi, dxi, d * 3 * J, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && idx) e = hipMemcpyAsync(idx, dS, sizeof(int32_t) * J * nn, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && w) e = hipMemcpyAsync(w, dw, d * J * nn, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    void *bufs[] = {djl, dxi, dS, dw};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    if (e != hipSuccess) return fail(c, RBFSL_E_DEVICE, "sample gather: %s", hipGetErrorString(e));
+    return RBFSL_OK;
+}
+
+#ifndef RBFSL_SOURCE_HASH
+#define RBFSL_SOURCE_HASH "unknown"
+#endif
+const char *rbfsl_source_hash(void) { return RBFSL_SOURCE_HASH; }
 
 void rbfsl_destroy(rbfsl_ctx *c) {
     if (!c) return;

@@ -22,9 +22,13 @@
 
 namespace rbfsl {
 
+// the largest harmonic basis a system can carry: (L+1)^2 <= n and
+// n + (L+1)^2 <= MAX_SYSTEM, so (L+1)^2 <= MAX_SYSTEM / 2
+constexpr int MAX_BASIS = MAX_SYSTEM / 2;
+
 template <int R>
 __global__ void __launch_bounds__(64) k_solve_cached(CachedArgs A) {
-    __shared__ double peb[64];  // basis values at the evaluation point
+    __shared__ double peb[MAX_BASIS];  // basis values at the evaluation point
     const int64_t j = blockIdx.x;
     const int lane = threadIdx.x;
     if (__builtin_amdgcn_readfirstlane(A.status[ST_FAILSTEP]) <= A.step) return;
@@ -52,7 +56,7 @@ __global__ void __launch_bounds__(64) k_solve_cached(CachedArgs A) {
     wave_lds_sync();
 
     // right-hand side, as the assembly builds it, moved to pivot order
-    __shared__ double yl[192];
+    __shared__ double yl[MAX_SYSTEM];
     const int32_t *Srow = A.S + K * n;
     const int32_t *stepof = A.stepof + K * M;
     sfor<0, R>([&](auto RI) SI {

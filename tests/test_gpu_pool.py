@@ -199,3 +199,11 @@ def test_served_results_equal_alone_and_in_the_mix():
             tr.run(it["nsteps"])
             alone = tr.get_q()
         assert np.array_equal(q, alone)
+        # and the oracle on the same request: a fault shared by both GPU
+        # paths (search, solver, apply) cannot hide behind the comparison above
+        pr = it["params"]
+        op = oracle.make_params(pr.n, pr.L, pr.k, 0, pr.velocity_id, list(pr.vel), pr.dt, pr.t0, pr.n_tracers)
+        qo, st, _ = oracle.run(it["nodes"], op, it["q0"], it["nsteps"])
+        assert st == oracle.ORC_OK
+        assert np.abs(q - qo).max() <= 1e-9
+        assert np.array_equal(q, qo)

@@ -59,3 +59,29 @@ def test_centre_mode_run_is_accurate():
     q, st, _ = oracle.run(X, p, q0, cfg["nsteps"])
     assert st == 0
     assert np.linalg.norm(q[0] - q0[0]) / np.linalg.norm(q0[0]) < 0.2
+
+
+def test_reversing_flow_returns_and_converges():
+    # The deformational flow reverses at T/2 and returns every parcel at T
+    # (the co-rotating stream function), so q(T) = q0 up to the interpolation
+    # error, which falls as N grows.  The flow is time dependent, so this also
+    # pins the time indexing of the run loop: traced with its times shifted by
+    # half a step or a whole step, the same run ends 0.17-0.31 away from q0 at
+    # both N (measured), whatever the resolution.
+    steps = 20
+    vp = W.deform_vp(kappa=0.5)
+    errs = []
+    for N in (2562, 10242):
+        X = W.fibonacci_nodes(N)
+        q0 = W.two_gaussians(X)[None]
+        p = oracle.make_params(31, 3, 2, 0, oracle.VEL_DEFORM, vp, 5.0 / steps, 0.0, 1)
+        half, st, _ = oracle.run(X, p, q0, steps // 2)
+        assert st == 0
+        # half way the bells are far from where they started
+        assert np.linalg.norm(half - q0) / np.linalg.norm(q0) > 1.0
+        q, st, _ = oracle.run(X, p, half, steps - steps // 2, m0=steps // 2)
+        assert st == 0
+        errs.append(np.linalg.norm(q - q0) / np.linalg.norm(q0))
+    # measured: 2.3e-2 and 2.6e-3 (3rd order in sqrt(N))
+    assert errs[1] < 5e-3
+    assert errs[0] / errs[1] > 4.0

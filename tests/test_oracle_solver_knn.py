@@ -104,3 +104,19 @@ def test_knn_duplicate_points_ordered_by_index():
     X = np.concatenate([X, X[[10, 3]]])  # nodes 64, 65 duplicate 10 and 3
     idx, _ = oracle.knn(X, X[[10]], 3)
     assert idx[0, :2].tolist() == [10, 64]
+
+
+@pytest.mark.parametrize("n", [1, 2, 31, 120, 700])
+def test_knn_selection_orders_of_arrival(n):
+    # the brute force keeps the n smallest keys while it scans the nodes in
+    # index order; Fibonacci nodes run from the north to the south pole, so
+    # queries at the poles see their neighbours arrive last (south) or first
+    # (north), and equatorial ones in the middle of the scan
+    X = W.fibonacci_nodes(700)
+    Q = np.array([[0.0, 0.0, -1.0], [0.0, 0.0, 1.0], [1.0, 0.0, 0.0], [0.0, -1.0, 0.0]])
+    Q = np.concatenate([Q, W.random_sphere_points(6, seed=n)])
+    idx, d2 = oracle.knn(X, Q, n)
+    for q in range(Q.shape[0]):
+        ref_i, ref_d = _numpy_knn(X, Q[q], n)
+        assert np.array_equal(idx[q], ref_i)
+        assert np.array_equal(d2[q], ref_d)

@@ -28,7 +28,13 @@ def monomials(L, P):
     return np.array(out)
 
 
-CASES = [(1024, 31, 3, 2), (2562, 17, 1, 1), (40962, 84, 5, 3), (4096, 56, 4, 2)]
+# (N, n, L, k): C1, a degree-one case, C2, the batched (56, 4, 2), and C3's
+# (120, 7, 4) on its 655,362 nodes, whose system has cond(A~) ~ 1.2e10.  The
+# partition-of-unity and reproduction residuals are rows of the system, which
+# backward-stable elimination satisfies to a few units of roundoff whatever
+# the conditioning (measured at C3: 1.1e-15 and 3.4e-16 sum|w|), so the same
+# bounds hold for every case.
+CASES = [(1024, 31, 3, 2), (2562, 17, 1, 1), (40962, 84, 5, 3), (4096, 56, 4, 2), (655362, 120, 7, 4)]
 
 
 @pytest.mark.parametrize("N,n,L,k", CASES)
@@ -42,6 +48,28 @@ def test_partition_of_unity_and_harmonic_reproduction(N, n, L, k):
         f0 = monomials(L, q[None])[:, 0]
         err = np.abs(F @ w - f0).max()
         assert err < 5e-13 * np.abs(w).sum()
+
+
+@pytest.mark.parametrize("N,n,L,k", [CASES[0], CASES[2], CASES[4]])
+def test_degree_above_L_is_not_reproduced(N, n, L, k):
+    # the reproduction pin has teeth: in coordinates centred at xi and scaled
+    # by the stencil radius s (the space of degree <= L is invariant under
+    # both), every monomial of degree <= L is reproduced to roundoff, while
+    # some monomial of degree L + 1 leaves an O(1e-5..1e-3) residual
+    # (measured at C1, C2, C3: 7e-4, 1e-5, 1.8e-5 against 7e-16, 2e-14, 1e-13)
+    q = W.random_sphere_points(1, seed=3)[0]
+    xs, s2 = stencil(N, n, q)
+    w, st = oracle.weights(n, L, k, xs, q, s2, q)
+    assert st == 0
+    Y = (xs - q) / np.sqrt(s2)
+    sw = np.abs(w).sum()
+    res = []
+    for deg in (L, L + 1):
+        F = monomials(deg, Y)
+        f0 = monomials(deg, np.zeros((1, 3)))[:, 0]
+        res.append(np.abs(F @ w - f0).max())
+    assert res[0] < 1e-11 * sw
+    assert res[1] > 1e-7 * sw
 
 
 @pytest.mark.parametrize("N,n,L,k", CASES[:2])
@@ -151,7 +179,12 @@ def mp_weights(xs, q, n, L, k, dps=40):
     return np.array([float(z[a]) for a in range(n)])
 
 
-@pytest.mark.parametrize("N,n,L,k,tol", [(1024, 31, 3, 2, 1e-12), (40962, 84, 5, 3, 1e-10)])
+# Forward error of the weights is bounded by about cond(A~) u (u = 1.1e-16):
+# C1 cond ~ 1e3, C2 ~ 6e7 (cond u = 7e-9), C3 ~ 1.2e10 (cond u = 1.3e-6);
+# each tolerance is cond u / 100, well above what is measured (C3: 3e-10) and
+# far below the O(1) change a dropped term, wrong sign or index would cause.
+@pytest.mark.parametrize("N,n,L,k,tol", [(1024, 31, 3, 2, 1e-12), (40962, 84, 5, 3, 1e-10),
+                                         pytest.param(655362, 120, 7, 4, 1e-8, marks=pytest.mark.slow)])
 def test_weights_match_40_digit_global_basis_solve(N, n, L, k, tol):
     q = W.random_sphere_points(1, 5)[0]
     xs, s2 = stencil(N, n, q)
