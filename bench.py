@@ -8,21 +8,27 @@ PHS + spherical-harmonic system, back substitution, gather-and-dot apply.
 Inputs are synthetic (spherical Fibonacci nodes, analytic flow, Gaussian
 fields) and resident in HBM before the timed region.
 
+The headline (the JSON line's value) is the largest configuration that fits
+one GPU: N = 655,362 nodes, (n, L, k) = (120, 7, 4) (M = 184 unknowns per
+system), eight tracers sharing each step's weights, deformational flow.
+
 Sections (all by default):
-  plain   -- the headline: one run, one launch sequence per step (the value);
+  plain   -- the headline: one run, one launch sequence per step;
+  c2, c1  -- the same for N = 40,962, (84, 5, 3) and N = 1,024, (31, 3, 2);
   batched -- 64 independent ragged runs advanced together by the pool (one
              search pass and one persistent solve launch per kernel family
              and step, graph-replayed, autotuned), against the same runs
              stepped one after another on the plain path;
   centre  -- the paper's centre-point stencils with every node's factorization
-             computed once and replayed each step (same C2 workload);
-  pu      -- the same workload interpolated by RBF-PU (patches factored once;
-             per step: patch search, patch coefficients, partition-of-unity
-             blend);
+             computed once and replayed each step (N = 40,962);
+  pu      -- the N = 40,962 workload interpolated by RBF-PU (patches factored
+             once; per step: patch search, patch coefficients,
+             partition-of-unity blend);
   served  -- a Poisson stream of transport requests (arrival rate 0.8 x the
              capacity calibrated on the request mix) through the pool's
              continuous-batching loop under a 200 GB HBM budget: p50/p99
-             request latency and aggregate throughput.
+             request latency and aggregate throughput, against the same
+             requests run one after another on the plain path.
 
 Prints one JSON line.  `--gpus N` with N > 1 is refused: this build runs on a
 single GPU (see the design notes on sharding).
@@ -61,11 +67,22 @@ def solve_flops(M):
     return elim + back
 
 
+def assembly_flops(n, L, k):
+    """Algorithmic flops of one stencil's assembly: the symmetric PHS block,
+    n^2/2 entries of (10 + k) flops (difference, squared distance, square
+    root, k products), and 3 n (L+1)^2 for the harmonic basis block."""
+    return n * n * (10 + k) // 2 + 3 * n * (L + 1) ** 2
+
+
+def stencil_flops(n, L, k):
+    return assembly_flops(n, L, k) + solve_flops(n + (L + 1) ** 2)
+
+
 def solver_sources_sha256(M):
     """Hash of the solver sources the counters were taken on (kernel + instantiation)."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_1804_01609_amd", "csrc")
-    cap = {47: 48}.get(M, M)
+    cap = {47: 48, 184: 192}.get(M, M)
     h = hashlib.sha256()
     for f in ("k_solve.h", f"k_solve_m{cap}.hip"):
         path = os.path.join(csrc, f)
@@ -75,12 +92,13 @@ def solver_sources_sha256(M):
     return h.hexdigest()
 
 
-def measured_traffic(cfg_key, M):
+def measured_traffic(cfg, M):
     """HBM bytes per k_solve launch from the committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE, each scaled by a known-size copy kernel), or None
     when the summary is missing or the solver sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", f"k_solve_{cfg_key}_N40962_M120_counters.txt")
-    if cfg_key != "c2" or not os.path.exists(path):
+    key = cfg["name"].split("-")[0]
+    path = os.path.join(ROOT, "profiles", f"k_solve_{key}_N{cfg['N']}_M{M}_counters.txt")
+    if not os.path.exists(path):
         return None
     kv = dict(line.strip().split("=", 1) for line in open(path) if "=" in line and not line.startswith("#"))
     if kv.get("source_sha256") != solver_sources_sha256(M):
@@ -88,34 +106,97 @@ def measured_traffic(cfg_key, M):
     return float(kv["hbm_bytes_per_launch"])
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(cfg, X, q0, target_s):
-    """The oracle, as it stands, on a bounded sample of one step's nodes."""
+    """The oracle, as it stands, on a bounded sample of one step's nodes: on
+    all host threads (the value) and on one thread."""
     import oracle
     p = oracle.make_params(cfg["n"], cfg["L"], cfg["k"], 0, cfg["vel_id"], cfg["vp"], cfg["dt"], 0.0, cfg["ntr"])
     rng = np.random.default_rng(0)
-    J = 512
-    t = time.perf_counter()
-    oracle.step_sample(X, p, 0, rng.integers(0, X.shape[0], J), q0)
-    dt = time.perf_counter() - t
-    J2 = int(min(X.shape[0], max(J, J * target_s / max(dt, 1e-6))))
-    jl = rng.integers(0, X.shape[0], J2)
-    t = time.perf_counter()
-    oracle.step_sample(X, p, 0, jl, q0)
-    dt2 = time.perf_counter() - t
-    return {"value": J2 / dt2, "unit": "interpolations/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"one step (step 0) of {cfg['name']} for {J2} randomly drawn nodes, "
-                      f"{dt2:.1f} s on {oracle.threads()} OpenMP threads"}
+    nthr = oracle.threads()
+
+    def rate(threads, seconds, probe):
+        oracle.set_threads(threads)
+        t = time.perf_counter()
+        oracle.step_sample(X, p, 0, rng.integers(0, X.shape[0], probe), q0)
+        dt = time.perf_counter() - t
+        J = int(min(X.shape[0], max(probe, probe * seconds / max(dt, 1e-6))))
+        t = time.perf_counter()
+        oracle.step_sample(X, p, 0, rng.integers(0, X.shape[0], J), q0)
+        dt = time.perf_counter() - t
+        return J / dt, J, dt
+
+    one, J1, t1 = rate(1, target_s / 4, 16)
+    allr, J, dt = rate(nthr, target_s, 16 * nthr)
+    oracle.set_threads(nthr)
+    return {"value": allr, "unit": "interpolations/s", "cores": nthr, "kind": "oracle",
+            "single_core_value": one, "cpu_model": cpu_model(),
+            "sample": f"one step (step 0) of {cfg['name']} for {J} randomly drawn nodes, {dt:.1f} s on "
+                      f"{nthr} OpenMP threads (one thread: {J1} nodes, {t1:.1f} s); per node: brute-force "
+                      f"n nearest of all N nodes kept in a heap, assembly, elimination, apply"}
+
+
+# steps and warm-up steps when not given: the headline configuration is timed
+# over a few steps (0.5 s each), the small ones over a full run
+STEP_DEFAULTS = {"c1": (128, 10), "c2": (480, 10), "c3": (20, 2)}
+
+
+def bench_plain(name, steps, warmup, sync):
+    """One run of configuration `name`: `steps` timed steps after `warmup`."""
+    cfg = W.CONFIGS[name]
+    N, n, L, k = cfg["N"], cfg["n"], cfg["L"], cfg["k"]
+    M = n + (L + 1) ** 2
+    X = W.fibonacci_nodes(N)
+    q0 = W.initial_q(cfg, X)
+    p = rb.make_params(n, L, k, 0, cfg["vel_id"], cfg["vp"], cfg["dt"], 0.0, cfg["ntr"])
+    tr = rb.Transport(X, p)
+    tr.set_q(q0)
+    if warmup:
+        tr.run(warmup)
+    tr.profile(True)
+    sync()
+    t0 = time.perf_counter()
+    tr.run(steps)  # one host synchronisation at the end
+    sync()
+    t1 = time.perf_counter()
+    phase_ms, nrec = tr.phase_times()
+    tr.profile(False)
+    tr.close()
+    elapsed = t1 - t0
+    solve_ms = phase_ms[2] / max(nrec, 1)
+    fl = stencil_flops(n, L, k) * N
+    achieved = fl / (solve_ms * 1e-3) / 1e12
+    return {
+        "workload": cfg["name"], "N": N, "n": n, "L": L, "k": k, "M": M, "tracers": cfg["ntr"], "dt": cfg["dt"],
+        "steps": steps, "warmup": warmup, "value": N * steps / elapsed, "unit": "interpolations/s",
+        "ms_per_step": 1e3 * elapsed / steps,
+        "phase_ms_per_step": {nm: phase_ms[i] / max(nrec, 1) for i, nm in enumerate(["trace", "knn", "solve", "apply"])},
+        "roofline": {"kernel": "k_solve", "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": measured_traffic(cfg, M), "traffic_unit": "bytes/launch",
+                     "flops_per_launch": fl, "flops_per_stencil": stencil_flops(n, L, k),
+                     "launch_ms": solve_ms},
+    }, X, q0
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=480)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--config", default="c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--sections", default="plain,centre,pu,batched,served")
+    ap.add_argument("--sections", default="plain,c2,c1,centre,pu,batched,served")
     ap.add_argument("--batched-steps", type=int, default=24)
     ap.add_argument("--served-requests", type=int, default=10)
     ap.add_argument("--served-step-scale", type=float, default=0.25,
@@ -140,69 +221,54 @@ def main():
                                    "(multi-GPU sharding is described in the design notes, not built)"}))
         sys.exit(2)
 
-    cfg = W.CONFIGS[args.config]
-    N, n, L, k = cfg["N"], cfg["n"], cfg["L"], cfg["k"]
-    M = n + (L + 1) ** 2
-    X = W.fibonacci_nodes(N)
-    q0 = W.initial_q(cfg, X)
-    p = rb.make_params(n, L, k, 0, cfg["vel_id"], cfg["vp"], cfg["dt"], 0.0, cfg["ntr"])
-
     try:
         import torch
         sync = torch.cuda.synchronize if torch.cuda.is_available() else (lambda: None)
     except Exception:
         sync = lambda: None  # noqa: E731
 
-    tr = rb.Transport(X, p)
-    tr.set_q(q0)
-    if args.warmup:
-        tr.run(args.warmup)
-    tr.profile(True)
-    sync()
-    t0 = time.perf_counter()
-    tr.run(args.steps)  # one host synchronisation at the end
-    sync()
-    t1 = time.perf_counter()
-    phase_ms, nrec = tr.phase_times()
-    tr.profile(False)
-    tr.close()
-
-    elapsed = t1 - t0
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = N * args.steps / elapsed
-    solve_ms = phase_ms[2] / max(nrec, 1)
-    fl = solve_flops(M) * N
-    achieved = fl / (solve_ms * 1e-3) / 1e12
+    steps = args.steps if args.steps is not None else STEP_DEFAULTS.get(args.config, (20, 2))[0]
+    warmup = args.warmup if args.warmup is not None else STEP_DEFAULTS.get(args.config, (20, 2))[1]
+    head, X, q0 = bench_plain(args.config, steps, warmup, sync)
+    cfg = W.CONFIGS[args.config]
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": head["value"],
         "unit": "interpolations/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": cfg["name"], "N": N, "n": n, "L": L, "k": k, "M": M,
-                   "tracers": cfg["ntr"], "dt": cfg["dt"], "mode": "plain, one run per launch sequence"},
-        "phase_ms_per_step": {name: phase_ms[i] / max(nrec, 1)
-                              for i, name in enumerate(["trace", "knn", "solve", "apply"])},
-        "roofline": {"kernel": "k_solve", "bound": "alu", "achieved": achieved,
-                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                     "traffic": measured_traffic(args.config, M), "traffic_unit": "bytes/launch",
-                     "flops_per_launch": fl, "launch_ms": solve_ms},
+        "config": {"workload": cfg["name"], "N": head["N"], "n": head["n"], "L": head["L"], "k": head["k"],
+                   "M": head["M"], "tracers": head["tracers"], "dt": head["dt"],
+                   "mode": "plain, one run per launch sequence"},
+        "phase_ms_per_step": head["phase_ms_per_step"],
+        "roofline": head["roofline"],
     }
-    say(f"plain: {value:.4g} interpolations/s, {ms_per_step:.3f} ms/step")
+    say(f"plain {cfg['name']}: {head['value']:.4g} interpolations/s, {head['ms_per_step']:.3f} ms/step, "
+        f"k_solve {head['roofline']['launch_ms']:.2f} ms = {head['roofline']['frac']:.4f} of FP64 peak")
     sections = set(args.sections.split(","))
+    for nm in ("c2", "c1"):
+        if nm in sections and nm != args.config:
+            st, wu = (100, 5) if nm == "c2" else STEP_DEFAULTS[nm]
+            r, _, _ = bench_plain(nm, st, wu, sync)
+            out[nm] = r
+            say(f"plain {r['workload']}: {r['value']:.4g} interpolations/s, {r['ms_per_step']:.3f} ms/step")
+    c2 = W.CONFIGS["c2"]
+    if "centre" in sections or "pu" in sections:
+        X2 = W.fibonacci_nodes(c2["N"])
+        q2 = W.initial_q(c2, X2)
     if "centre" in sections:
-        out["centre"] = bench_centre(cfg, X, q0, sync)
+        out["centre"] = bench_centre(c2, X2, q2, sync)
         say(f"centre (cached factors): {out['centre']['value']:.4g} interpolations/s, "
             f"{out['centre']['ms_per_step']:.3f} ms/step")
     if "pu" in sections:
-        out["pu"] = bench_pu(cfg, X, q0, sync)
+        out["pu"] = bench_pu(c2, X2, q2, sync)
         say(f"RBF-PU: {out['pu']['value']:.4g} interpolations/s, {out['pu']['ms_per_step']:.3f} ms/step")
     if "batched" in sections:
         out["batched"] = bench_batched(args.batched_steps, sync)

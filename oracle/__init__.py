@@ -57,6 +57,7 @@ def lib():
             build()
         L = ctypes.CDLL(_SO)
         L.orc_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_velocity.argtypes = [ctypes.c_int, _D, ctypes.c_double, _D, _D]
         L.orc_trace.argtypes = [ctypes.c_int64, _D, ctypes.c_int, _D, ctypes.c_int, ctypes.c_double,
                                 ctypes.c_double, ctypes.c_int64, _D]
@@ -101,6 +102,11 @@ def _f64(a, shape=None):
 
 def threads():
     return lib().orc_threads()
+
+
+def set_threads(n):
+    """Threads of the oracle's later parallel loops."""
+    lib().orc_set_threads(int(n))
 
 
 def make_params(n, L, k, mode=0, vel_id=VEL_ZERO, vp=(), dt=0.0, t0=0.0, ntr=1, rk=RK4):

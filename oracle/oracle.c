@@ -74,6 +74,15 @@ int orc_threads(void) {
 #endif
 }
 
+/* threads used by later parallel regions (timing on one core or all) */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Velocity fields (Section 4.1 solid body; the time-reversing stream-       */
 /* function flow of the transport problem).                                   */

@@ -194,32 +194,16 @@ __device__ __forceinline__ double wave_max_nonneg(double v) {
 }
 
 
-// Assembles and solves one system with the W waves of a stencil group;
-// t = thread index inside the group (0 .. 64W-1), block-wide barriers.
-// Returns false when elimination met a column with no usable pivot (the
-// system is singular to working precision); else the solution is in sh.zb.
-// LOCK: several groups of one workgroup run this in lockstep on systems of
-// the same size, so every group passes every barrier: a singular group keeps
-// going (on values that are then discarded) instead of leaving early.
-template <int W, int R, int NCB, int B, bool LOCK, int CM = 24, bool FACT = false>
-__device__ __forceinline__ bool solve_system(SolveSmem<W, R, NCB, B, CM> &sh, const int t, const SysIn &A,
-                                             const FactorOut *fo = nullptr) {
+// Assembly of one system (eq. rbf_poly_linsys in the local graded basis):
+// this lane's rows (i = lane + 64 r) of this wave's columns go to a, the
+// right-hand side [b; p(xi)] of the same rows to y.  stage holds the local
+// coordinates and basis tables; one barrier between filling and reading them.
+template <int W, int R, int NCB, int B, int CM = 24>
+__device__ __forceinline__ void assemble_system(double *const stage, const int t, const SysIn &A,
+                                                double (&a)[R][Cfg<W, R, NCB, B, 1, CM>::NC], double (&y)[R]) {
     using C = Cfg<W, R, NCB, B, 1, CM>;
-    constexpr int NT = C::NT, ROWS = C::ROWS, MCAP = C::MCAP, NC = C::NC;
-    double *const stage = sh.stage;
-    double *const rinvb = sh.rinvb;
-    double *const zb = sh.zb;
-    int *const pivb = sh.pivb;
-    int *const failk = sh.failk;
-    double(*lb)[B][ROWS] = reinterpret_cast<double(*)[B][ROWS]>(stage);  // [2][B][ROWS]
-    constexpr int NOFAIL = 0x7fffffff;
-
+    constexpr int NT = C::NT, MCAP = C::MCAP, NC = C::NC;
     const int lane = t & 63, wv = t >> 6;
-    if (t == 0) {  // read after the assembly barriers
-        failk[0] = NOFAIL;
-        failk[1] = NOFAIL;
-    }
-
     const int n = A.n, L = A.L, k = A.k;
     const int mL = (L + 1) * (L + 1);
     const int M = n + mL;
@@ -252,58 +236,178 @@ __device__ __forceinline__ bool solve_system(SolveSmem<W, R, NCB, B, CM> &sh, co
         } else {
             x[0] = xe[0]; x[1] = xe[1]; x[2] = xe[2];
         }
-        double y[3], al, be, u;
-        local3(x, ctr, e1, e2, inv_s, y, al, be, u);
+        double yl[3], al, be, u;
+        local3(x, ctr, e1, e2, inv_s, yl, al, be, u);
         if (a < n) {
-            yb[3 * a] = y[0]; yb[3 * a + 1] = y[1]; yb[3 * a + 2] = y[2];
+            yb[3 * a] = yl[0]; yb[3 * a + 1] = yl[1]; yb[3 * a + 2] = yl[2];
             basis_all(L, al, be, u, Pb + a * mL);
         } else {
-            yxb[0] = y[0]; yxb[1] = y[1]; yxb[2] = y[2];
+            yxb[0] = yl[0]; yxb[1] = yl[1]; yxb[2] = yl[2];
             basis_all(L, al, be, u, peb);
         }
     }
     __syncthreads();
 
     // ---- assembly 2: my rows, my columns; the right-hand side ----
-    double a[R][NC];
-    double y[R];
-    bool used[R];
-    int stepof[R];
-    {
-        const double yx0 = yxb[0], yx1 = yxb[1], yx2 = yxb[2];
-        sfor<0, R>([&](auto RI) SI {
-            constexpr int r = RI;
-            const int i = lane + 64 * r;
-            used[r] = (i >= M);
-            stepof[r] = MCAP;
-            double yi0 = 0.0, yi1 = 0.0, yi2 = 0.0;
-            if (i < n) { yi0 = yb[3 * i]; yi1 = yb[3 * i + 1]; yi2 = yb[3 * i + 2]; }
-            double rhs = 0.0;
+    const double yx0 = yxb[0], yx1 = yxb[1], yx2 = yxb[2];
+    sfor<0, R>([&](auto RI) SI {
+        constexpr int r = RI;
+        const int i = lane + 64 * r;
+        double yi0 = 0.0, yi1 = 0.0, yi2 = 0.0;
+        if (i < n) { yi0 = yb[3 * i]; yi1 = yb[3 * i + 1]; yi2 = yb[3 * i + 2]; }
+        double rhs = 0.0;
+        if (i < n) {
+            double d0 = yi0 - yx0, d1 = yi1 - yx1, d2 = yi2 - yx2;
+            rhs = phs((d0 * d0 + d1 * d1) + d2 * d2, k);
+        } else if (i < M) {
+            rhs = peb[i - n];
+        }
+        y[r] = rhs;
+        sfor<0, NC>([&](auto S) SI {
+            constexpr int sl = S;
+            const int jc = ((sl / B) * W + wv) * B + sl % B;
+            double v = 0.0;
             if (i < n) {
-                double d0 = yi0 - yx0, d1 = yi1 - yx1, d2 = yi2 - yx2;
-                rhs = phs((d0 * d0 + d1 * d1) + d2 * d2, k);
-            } else if (i < M) {
-                rhs = peb[i - n];
-            }
-            y[r] = rhs;
-            sfor<0, NC>([&](auto S) SI {
-                constexpr int sl = S;
-                const int jc = ((sl / B) * W + wv) * B + sl % B;
-                double v = 0.0;
-                if (i < n) {
-                    if (jc < n) {
-                        double d0 = yi0 - yb[3 * jc], d1 = yi1 - yb[3 * jc + 1], d2 = yi2 - yb[3 * jc + 2];
-                        v = phs((d0 * d0 + d1 * d1) + d2 * d2, k);
-                    } else if (jc < M) {
-                        v = Pb[i * mL + (jc - n)];
-                    }
-                } else if (i < M) {
-                    if (jc < n) v = Pb[jc * mL + (i - n)];
+                if (jc < n) {
+                    double d0 = yi0 - yb[3 * jc], d1 = yi1 - yb[3 * jc + 1], d2 = yi2 - yb[3 * jc + 2];
+                    v = phs((d0 * d0 + d1 * d1) + d2 * d2, k);
+                } else if (jc < M) {
+                    v = Pb[i * mL + (jc - n)];
                 }
-                a[r][sl] = v;
+            } else if (i < M) {
+                if (jc < n) v = Pb[jc * mL + (i - n)];
+            }
+            a[r][sl] = v;
+        });
+    });
+}
+
+// Back substitution (after the elimination of solve_system or
+// solve_system_df), chunks of CSB slot-blocks from the right: slot-blocks
+// [sb1, sb2) of every wave cover columns [sb1*W*B, sb2*W*B); wave 0 holds the
+// pivot rows in registers (lane k % 64, slot k / 64) and, for each of its
+// rows, the reciprocal of the pivot of the step at which the row was the
+// pivot row.  Unknown k is z_k = y_p * r_k with p the pivot row of step k: it
+// is formed in row p's lane and broadcast.  A row's y is final once its own
+// step is reached, so every unknown is again y_p * r_k at the end, where
+// wave 0 writes them all to zb at once.  Ends with a barrier.
+template <int W, int R, int NCB, int B, int CM = 24>
+__device__ __forceinline__ void back_substitute(double *const stage, const double *const rinvb,
+                                                const int *const pivb, double *const zb, const int (&stepof)[R],
+                                                const double (&a)[R][Cfg<W, R, NCB, B, 1, CM>::NC],
+                                                double (&y)[R], const int t, const int M) {
+    using C = Cfg<W, R, NCB, B, 1, CM>;
+    constexpr int ROWS = C::ROWS, MCAP = C::MCAP;
+    const int lane = t & 63, wv = t >> 6;
+    constexpr int KT = (MCAP + 63) / 64;
+    int pivr[KT];
+    sfor<0, KT>([&](auto TI) SI {
+        constexpr int tt = TI;
+        const int kk = lane + 64 * tt;
+        pivr[tt] = (kk < M) ? pivb[kk] : 0;
+    });
+    double rrow[R];
+    sfor<0, R>([&](auto RI) SI {
+        constexpr int r = RI;
+        rrow[r] = (stepof[r] < M) ? rinvb[stepof[r]] : 0.0;
+    });
+    double *UB = stage;
+    sfor<0, C::NCHUNK>([&](auto CI) SI {
+        constexpr int ch = C::NCHUNK - 1 - CI;
+        constexpr int sb1 = ch * C::CSB;
+        constexpr int sb2 = (sb1 + C::CSB < NCB) ? sb1 + C::CSB : NCB;
+        constexpr int c0 = sb1 * W * B;
+        if (c0 >= M) return;  // chunk lies beyond the last column
+        __syncthreads();      // previous chunk consumed
+        sfor<sb1 * B, sb2 * B>([&](auto S) SI {
+            constexpr int sl = S;
+            const int col = ((sl / B) * W + wv) * B + sl % B - c0;
+            sfor<0, R>([&](auto RI) SI {
+                constexpr int r = RI;
+                UB[col * ROWS + lane + 64 * r] = a[r][sl];
             });
         });
+        __syncthreads();
+        if (wv == 0) {
+            const int khi = (sb2 * W * B < M) ? sb2 * W * B : M;
+            double un[R];
+            sfor<0, R>([&](auto RI) SI { un[RI] = UB[(khi - 1 - c0) * ROWS + lane + 64 * RI]; });
+            for (int kk = khi - 1; kk >= c0; --kk) {
+                double u[R];
+                sfor<0, R>([&](auto RI) SI { u[RI] = un[RI]; });
+                const int kn = (kk > c0) ? kk - 1 : c0;
+                sfor<0, R>([&](auto RI) SI { un[RI] = UB[(kn - c0) * ROWS + lane + 64 * RI]; });
+                const int kl = kk & 63, kt = kk >> 6;
+                // pivot row of step kk (register slot kt, lane kl)
+                int pk = __builtin_amdgcn_readlane(pivr[0], kl);
+                sfor<1, KT>([&](auto TI) SI {
+                    constexpr int tt = TI;
+                    const int pt = __builtin_amdgcn_readlane(pivr[tt], kl);
+                    pk = (kt == tt) ? pt : pk;
+                });
+                const int pl = pk & 63, pr = pk >> 6;
+                double ysel = y[0], rsel = rrow[0];
+                sfor<1, R>([&](auto RI) SI {
+                    constexpr int r = RI;
+                    ysel = (pr == r) ? y[r] : ysel;
+                    rsel = (pr == r) ? rrow[r] : rsel;
+                });
+                const double zk = bcast_d(ysel * rsel, pl);
+                sfor<0, R>([&](auto RI) SI {
+                    constexpr int r = RI;
+                    const double yn = fma(-u[r], zk, y[r]);
+                    y[r] = (stepof[r] < kk) ? yn : y[r];
+                });
+            }
+        }
+    });
+    if (wv == 0) {
+        sfor<0, R>([&](auto RI) SI {
+            constexpr int r = RI;
+            if (stepof[r] < M) zb[stepof[r]] = y[r] * rrow[r];
+        });
     }
+    __syncthreads();
+}
+
+// Assembles and solves one system with the W waves of a stencil group;
+// t = thread index inside the group (0 .. 64W-1), block-wide barriers.
+// Returns false when elimination met a column with no usable pivot (the
+// system is singular to working precision); else the solution is in sh.zb.
+// LOCK: several groups of one workgroup run this in lockstep on systems of
+// the same size, so every group passes every barrier: a singular group keeps
+// going (on values that are then discarded) instead of leaving early.
+template <int W, int R, int NCB, int B, bool LOCK, int CM = 24, bool FACT = false>
+__device__ __forceinline__ bool solve_system(SolveSmem<W, R, NCB, B, CM> &sh, const int t, const SysIn &A,
+                                             const FactorOut *fo = nullptr) {
+    using C = Cfg<W, R, NCB, B, 1, CM>;
+    constexpr int NT = C::NT, ROWS = C::ROWS, MCAP = C::MCAP, NC = C::NC;
+    double *const stage = sh.stage;
+    double *const rinvb = sh.rinvb;
+    double *const zb = sh.zb;
+    int *const pivb = sh.pivb;
+    int *const failk = sh.failk;
+    double(*lb)[B][ROWS] = reinterpret_cast<double(*)[B][ROWS]>(stage);  // [2][B][ROWS]
+    constexpr int NOFAIL = 0x7fffffff;
+
+    const int lane = t & 63, wv = t >> 6;
+    if (t == 0) {  // read after the assembly barriers
+        failk[0] = NOFAIL;
+        failk[1] = NOFAIL;
+    }
+
+    const int n = A.n, L = A.L;
+    const int mL = (L + 1) * (L + 1);
+    const int M = n + mL;
+    double a[R][NC];
+    double y[R];
+    assemble_system<W, R, NCB, B, CM>(stage, t, A, a, y);
+    bool used[R];
+    int stepof[R];
+    sfor<0, R>([&](auto RI) SI {
+        used[RI] = (lane + 64 * RI >= M);
+        stepof[RI] = MCAP;
+    });
 
     __syncthreads();  // the assembly tables are dead; stage now holds multipliers
 
@@ -471,83 +575,7 @@ __device__ __forceinline__ bool solve_system(SolveSmem<W, R, NCB, B, CM> &sh, co
         return true;
     }
 
-    // ---- back substitution, chunks of CSB slot-blocks from the right ----
-    // slot-blocks [sb1, sb2) of every wave cover columns [sb1*W*B, sb2*W*B);
-    // wave 0 holds the pivot rows in registers (lane k % 64, slot k / 64) and,
-    // for each of its rows, the reciprocal of the pivot of the step at which
-    // the row was the pivot row.  Unknown k is z_k = y_p * r_k with p the
-    // pivot row of step k: it is formed in row p's lane and broadcast.  A
-    // row's y is final once its own step is reached, so every unknown is
-    // again y_p * r_k at the end, where wave 0 writes them all at once.
-    constexpr int KT = (MCAP + 63) / 64;
-    int pivr[KT];
-    sfor<0, KT>([&](auto TI) SI {
-        constexpr int tt = TI;
-        const int kk = lane + 64 * tt;
-        pivr[tt] = (kk < M) ? pivb[kk] : 0;
-    });
-    double rrow[R];
-    sfor<0, R>([&](auto RI) SI {
-        constexpr int r = RI;
-        rrow[r] = (stepof[r] < M) ? rinvb[stepof[r]] : 0.0;
-    });
-    double *UB = stage;
-    sfor<0, C::NCHUNK>([&](auto CI) SI {
-        constexpr int ch = C::NCHUNK - 1 - CI;
-        constexpr int sb1 = ch * C::CSB;
-        constexpr int sb2 = (sb1 + C::CSB < NCB) ? sb1 + C::CSB : NCB;
-        constexpr int c0 = sb1 * W * B;
-        if (c0 >= M) return;  // chunk lies beyond the last column
-        __syncthreads();      // previous chunk consumed
-        sfor<sb1 * B, sb2 * B>([&](auto S) SI {
-            constexpr int sl = S;
-            const int col = ((sl / B) * W + wv) * B + sl % B - c0;
-            sfor<0, R>([&](auto RI) SI {
-                constexpr int r = RI;
-                UB[col * ROWS + lane + 64 * r] = a[r][sl];
-            });
-        });
-        __syncthreads();
-        if (wv == 0) {
-            const int khi = (sb2 * W * B < M) ? sb2 * W * B : M;
-            double un[R];
-            sfor<0, R>([&](auto RI) SI { un[RI] = UB[(khi - 1 - c0) * ROWS + lane + 64 * RI]; });
-            for (int kk = khi - 1; kk >= c0; --kk) {
-                double u[R];
-                sfor<0, R>([&](auto RI) SI { u[RI] = un[RI]; });
-                const int kn = (kk > c0) ? kk - 1 : c0;
-                sfor<0, R>([&](auto RI) SI { un[RI] = UB[(kn - c0) * ROWS + lane + 64 * RI]; });
-                const int kl = kk & 63, kt = kk >> 6;
-                // pivot row of step kk (register slot kt, lane kl)
-                int pk = __builtin_amdgcn_readlane(pivr[0], kl);
-                sfor<1, KT>([&](auto TI) SI {
-                    constexpr int tt = TI;
-                    const int pt = __builtin_amdgcn_readlane(pivr[tt], kl);
-                    pk = (kt == tt) ? pt : pk;
-                });
-                const int pl = pk & 63, pr = pk >> 6;
-                double ysel = y[0], rsel = rrow[0];
-                sfor<1, R>([&](auto RI) SI {
-                    constexpr int r = RI;
-                    ysel = (pr == r) ? y[r] : ysel;
-                    rsel = (pr == r) ? rrow[r] : rsel;
-                });
-                const double zk = bcast_d(ysel * rsel, pl);
-                sfor<0, R>([&](auto RI) SI {
-                    constexpr int r = RI;
-                    const double yn = fma(-u[r], zk, y[r]);
-                    y[r] = (stepof[r] < kk) ? yn : y[r];
-                });
-            }
-        }
-    });
-    if (wv == 0) {
-        sfor<0, R>([&](auto RI) SI {
-            constexpr int r = RI;
-            if (stepof[r] < M) zb[stepof[r]] = y[r] * rrow[r];
-        });
-    }
-    __syncthreads();
+    back_substitute<W, R, NCB, B, CM>(stage, rinvb, pivb, zb, stepof, a, y, t, M);
 
     return !dead;
 }
