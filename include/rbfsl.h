@@ -52,7 +52,8 @@ enum {
     RBFSL_E_NONFINITE = -5, /* a stencil produced non-finite weights */
     RBFSL_E_STATE = -6,     /* call not valid in the current state (e.g. q not set) */
     RBFSL_E_SEARCH = -7,    /* the neighbour search could not bound a stencil */
-    RBFSL_E_BUDGET = -8     /* a pool has no free run slot or HBM for the run */
+    RBFSL_E_BUDGET = -8,    /* a pool has no free run slot or HBM for the run */
+    RBFSL_E_CAPACITY = -9   /* input larger than rbfsl_weights_noalloc's fixed scratch */
 };
 
 /* Velocity fields u(x,t) (tangent to the sphere, divergence free).
@@ -204,6 +205,26 @@ int rbfsl_knn(const double *nodes_xyz, int64_t N, const double *queries, int64_t
 int rbfsl_weights(const double *nodes_xyz, int64_t N, const int32_t *idx, const double *centers,
                   const double *s2, const double *evals, int64_t count, int32_t n, int32_t L,
                   int32_t k, double *w, int32_t *status, int on_device, void *hip_stream);
+
+/* rbfsl_weights for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same weights, bit for bit, computed without any allocation.  Every
+ * array is device memory on the current device (nodes_xyz N x 3, idx count x n,
+ * centers and evals count x 3, s2 count; outputs w count x n and status count,
+ * status may be NULL); a host pointer is RBFSL_E_INVAL.  The work is only
+ * enqueued on hip_stream (NULL = default stream): the outputs are valid once
+ * the stream has reached this point; nothing is synchronised.  The library's
+ * scratch for it (the coordinates as separate x, y, z arrays and the status
+ * words) is one fixed device array per GPU, held until the process ends, of
+ * 3 (N + 2 count) doubles at most: N + 2 count <= rbfsl_weights_noalloc_capacity()
+ * (2,097,152; 48 MiB), else RBFSL_E_CAPACITY and nothing is enqueued.  Calls
+ * that overlap on one GPU (other streams, other host threads) share that
+ * array and race; serialise them. */
+int rbfsl_weights_noalloc(const double *nodes_xyz, int64_t N, const int32_t *idx, const double *centers,
+                          const double *s2, const double *evals, int64_t count, int32_t n, int32_t L,
+                          int32_t k, double *w, int32_t *status, void *hip_stream);
+/* The largest N + 2 count rbfsl_weights_noalloc accepts. */
+int64_t rbfsl_weights_noalloc_capacity(void);
 
 /* Largest supported system size n + (L+1)^2. */
 int rbfsl_max_system(void);

@@ -25,6 +25,7 @@ RBFSL_E_NONFINITE = -5
 RBFSL_E_STATE = -6
 RBFSL_E_SEARCH = -7
 RBFSL_E_BUDGET = -8
+RBFSL_E_CAPACITY = -9
 
 VEL_ZERO, VEL_SOLID_BODY, VEL_DEFORM, VEL_NL2010 = 0, 1, 2, 3
 STENCIL_PU = 2  # RBF-PU (PuTransport)
@@ -33,7 +34,7 @@ RK4, RK5_FEHLBERG = 0, 1
 EXPORTS = [
     "rbfsl_create", "rbfsl_set_q", "rbfsl_step", "rbfsl_run", "rbfsl_get_q", "rbfsl_get_state",
     "rbfsl_get_failures", "rbfsl_profile", "rbfsl_phase_times", "rbfsl_debug_departure", "rbfsl_debug_stencils", "rbfsl_debug_weights",
-    "rbfsl_debug_sample", "rbfsl_source_hash",
+    "rbfsl_debug_sample", "rbfsl_source_hash", "rbfsl_weights_noalloc", "rbfsl_weights_noalloc_capacity",
     "rbfsl_knn", "rbfsl_weights", "rbfsl_max_system", "rbfsl_strerror", "rbfsl_last_error",
     "rbfsl_destroy", "rbfsl_create_pu", "rbfsl_pu_info", "rbfsl_debug_patches",
     "rbfsl_pool_create", "rbfsl_pool_run_bytes", "rbfsl_pool_add", "rbfsl_pool_step", "rbfsl_pool_run_info",
@@ -124,6 +125,8 @@ def lib():
         L.rbfsl_debug_patches.argtypes = [_P, _P, _P]
         L.rbfsl_knn.argtypes = [_P, i64, _P, i64, i32, _P, _P, ctypes.c_int, _P]
         L.rbfsl_weights.argtypes = [_P, i64, _P, _P, _P, _P, i64, i32, i32, i32, _P, _P, ctypes.c_int, _P]
+        L.rbfsl_weights_noalloc.argtypes = [_P, i64, _P, _P, _P, _P, i64, i32, i32, i32, _P, _P, _P]
+        L.rbfsl_weights_noalloc_capacity.restype = i64
         L.rbfsl_max_system.restype = ctypes.c_int
         L.rbfsl_strerror.restype = ctypes.c_char_p
         L.rbfsl_strerror.argtypes = [ctypes.c_int]
@@ -390,6 +393,40 @@ def weights(nodes, idx, centers, s2, evals, n, L, k):
                                evals.ctypes.data_as(_P), count, int(n), int(L), int(k),
                                w.ctypes.data_as(_P), st.ctypes.data_as(_P), 0, None))
     return w, st
+
+
+def weights_noalloc_ptr(nodes, N, idx, centers, s2, evals, count, n, L, k, w, status=0, stream=0):
+    """rbfsl_weights_noalloc on raw device addresses (ints): nodes N x 3,
+    idx count x n (int32), centers and evals count x 3, s2 count, outputs w
+    count x n and status count (0: none); enqueued on `stream` (0: default).
+    Returns the status code without raising."""
+    P = ctypes.c_void_p
+    return lib().rbfsl_weights_noalloc(P(nodes), int(N), P(idx), P(centers), P(s2), P(evals), int(count), int(n),
+                                       int(L), int(k), P(w), P(status) if status else None,
+                                       P(stream) if stream else None)
+
+
+def weights_noalloc_code(nodes, idx, centers, s2, evals, n, L, k, w, status=None, stream=None):
+    """rbfsl_weights_noalloc on device tensors (torch, float64 / int32,
+    contiguous): nodes (N, 3), idx (count, n), centers and evals (count, 3),
+    s2 (count,), outputs w (count, n) and status (count,) or None.  Work is
+    enqueued on `stream` (raw hipStream_t) or torch's current stream; returns
+    the status code without raising."""
+    args = []
+    for x, dt in ((nodes, np.float64), (idx, np.int32), (centers, np.float64), (s2, np.float64),
+                  (evals, np.float64), (w, np.float64)):
+        if not _is_torch(x):
+            raise TypeError("rbfsl_weights_noalloc takes device tensors")
+        args.append(_ptr(x, dt)[0])
+    st = _ptr(status, np.int32)[0] if status is not None else None
+    count = int(idx.shape[0])
+    s = ctypes.c_void_p(stream) if stream is not None else _stream(1)
+    return lib().rbfsl_weights_noalloc(args[0], int(nodes.shape[0]), args[1], args[2], args[3], args[4], count,
+                                       int(n), int(L), int(k), args[5], st, s)
+
+
+def weights_noalloc_capacity():
+    return lib().rbfsl_weights_noalloc_capacity()
 
 
 def max_system():

@@ -364,6 +364,10 @@ namespace rbfsl {
 
 StepCoef step_coef(const rbfsl_params &p, int64_t m) { return make_step_coef(p, m); }
 
+int resolve_stencil(int64_t N, int n, int L, int k, int *Lo, int *ko, char *msg, size_t msz) {
+    return resolve_nlk(N, n, L, k, Lo, ko, msg, msz);
+}
+
 int validate_params(int64_t N, const rbfsl_params *p, int *L, int *k, char *msg, size_t msz) {
     msg[0] = 0;
     if (N < 1 || N > 0x7fffffffLL) {
@@ -424,6 +428,7 @@ const char *rbfsl_strerror(int code) {
         case RBFSL_E_STATE: return "invalid state";
         case RBFSL_E_SEARCH: return "neighbour search failed";
         case RBFSL_E_BUDGET: return "no free run slot or HBM budget";
+        case RBFSL_E_CAPACITY: return "input larger than the fixed scratch of the no-allocation entry point";
         default: return "unknown status";
     }
 }

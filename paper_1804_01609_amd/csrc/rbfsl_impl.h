@@ -203,6 +203,8 @@ hipError_t launch_status_reset(int *status, hipStream_t s);
 // validated (n, L, k) of a parameter set for N nodes; RBFSL_E_INVAL with a
 // message otherwise
 int validate_params(int64_t N, const rbfsl_params *p, int *L, int *k, char *msg, size_t msz);
+// validated (n, L, k) alone (L = -1 / k = -1 select the paper's rule)
+int resolve_stencil(int64_t N, int n, int L, int k, int *Lo, int *ko, char *msg, size_t msz);
 StepCoef step_coef(const rbfsl_params &p, int64_t m);  // p with resolved L, k
 // N x 3 AoS (host or device) -> SoA device arrays, through `tmp` (3N doubles)
 hipError_t upload_points_via(const double *xyz, int64_t N, int on_device, double *x, double *y,
