@@ -163,6 +163,7 @@ def bench_plain(name, steps, warmup, sync):
     if warmup:
         tr.run(warmup)
     tr.profile(True)
+    spl = tr.steps_per_launch(steps)
     sync()
     t0 = time.perf_counter()
     tr.run(steps)  # one host synchronisation at the end
@@ -183,8 +184,8 @@ def bench_plain(name, steps, warmup, sync):
         "roofline": {"kernel": "k_solve", "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": measured_traffic(cfg, M), "traffic_unit": "bytes/launch",
-                     "flops_per_launch": fl, "flops_per_stencil": stencil_flops(n, L, k),
-                     "launch_ms": solve_ms},
+                     "flops_per_launch": fl * spl, "flops_per_stencil": stencil_flops(n, L, k),
+                     "launch_ms": solve_ms * spl, "steps_per_launch": spl},
     }, X, q0
 
 

@@ -153,8 +153,22 @@ int rbfsl_step(rbfsl_ctx *ctx);
 /* nsteps passes of Algorithm 1's loop (each as rbfsl_step), enqueued without
  * host synchronisation between them; one synchronisation at the end.  If step
  * f fails, later steps do nothing and the state is left at step f (q^f), with
- * the failure code returned. */
+ * the failure code returned.  The results are those of nsteps rbfsl_step
+ * calls, bit for bit.  Small problems (stencil modes 0 and 1 without cached
+ * factors, N <= 65,536) take several steps per launch: a step's departure
+ * points, stencils and weights do not depend on q (the velocity is
+ * prescribed, eq. sl_ode), so the tracer, search and solve of K consecutive
+ * steps each run as one launch over K N points (K = rbfsl_steps_per_launch),
+ * then the K field updates follow in step order.  In that mode the failure
+ * counts of rbfsl_get_failures may include stencils of steps after the first
+ * failing one (their launch had already started); the failing step, the
+ * state and q are as above.  After the run, the debug taps show the run's
+ * last step. */
 int rbfsl_run(rbfsl_ctx *ctx, int64_t nsteps);
+
+/* Steps per launch that rbfsl_run(ctx, nsteps) takes: 1 for the step-by-step
+ * path, else K >= 2 (131,072 / N stencils, at most 128 and nsteps). */
+int64_t rbfsl_steps_per_launch(const rbfsl_ctx *ctx, int64_t nsteps);
 
 /* Copy q^m, Algorithm 1's state after m steps, out (n_tracers x N).
  * Synchronises. */

@@ -32,7 +32,8 @@ STENCIL_PU = 2  # RBF-PU (PuTransport)
 RK4, RK5_FEHLBERG = 0, 1
 
 EXPORTS = [
-    "rbfsl_create", "rbfsl_set_q", "rbfsl_step", "rbfsl_run", "rbfsl_get_q", "rbfsl_get_state",
+    "rbfsl_create", "rbfsl_set_q", "rbfsl_step", "rbfsl_run", "rbfsl_steps_per_launch", "rbfsl_get_q",
+    "rbfsl_get_state",
     "rbfsl_get_failures", "rbfsl_profile", "rbfsl_phase_times", "rbfsl_debug_departure", "rbfsl_debug_stencils", "rbfsl_debug_weights",
     "rbfsl_debug_sample", "rbfsl_source_hash", "rbfsl_weights_noalloc", "rbfsl_weights_noalloc_capacity",
     "rbfsl_knn", "rbfsl_weights", "rbfsl_max_system", "rbfsl_strerror", "rbfsl_last_error",
@@ -109,6 +110,8 @@ def lib():
         L.rbfsl_set_q.argtypes = [_P, _P, ctypes.c_int]
         L.rbfsl_step.argtypes = [_P]
         L.rbfsl_run.argtypes = [_P, i64]
+        L.rbfsl_steps_per_launch.argtypes = [_P, i64]
+        L.rbfsl_steps_per_launch.restype = i64
         L.rbfsl_get_q.argtypes = [_P, _P, ctypes.c_int]
         L.rbfsl_get_state.argtypes = [_P, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
         L.rbfsl_get_failures.argtypes = [_P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
@@ -257,6 +260,10 @@ class Transport:
 
     def run(self, nsteps):
         _check(lib().rbfsl_run(self._ctx, int(nsteps)), self._ctx)
+
+    def steps_per_launch(self, nsteps):
+        """Steps per launch that run(nsteps) takes (1: step by step)."""
+        return int(lib().rbfsl_steps_per_launch(self._ctx, int(nsteps)))
 
     def run_status(self, nsteps):
         """run() returning the status code instead of raising."""

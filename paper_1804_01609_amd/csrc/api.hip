@@ -43,6 +43,16 @@ struct rbfsl_ctx {
     Grid cgrid;
     double *q[2] = {nullptr, nullptr};
     int cur = 0;
+    // several steps per launch (runs of small problems): departure points,
+    // stencils and weights of up to ahead_cap steps, their tracer
+    // coefficients (device, and pinned staging by chunk parity)
+    int64_t ahead_cap = 0;
+    double *aex = nullptr, *aey = nullptr, *aez = nullptr, *as2 = nullptr, *aw = nullptr;
+    int32_t *aS = nullptr, *acidx = nullptr;
+    StepCoef *asc = nullptr;
+    StepCoef *asc_host[2] = {nullptr, nullptr};
+    hipEvent_t asc_done[2] = {nullptr, nullptr};
+    bool asc_used[2] = {false, false};
     int *status = nullptr;
     int64_t step = 0;
     bool q_set = false, ran = false;
@@ -51,6 +61,7 @@ struct rbfsl_ctx {
     bool prof = false;
     std::vector<hipEvent_t> ev;  // 5 per recorded step
     int64_t ev_used = 0, prof_steps = 0;
+    std::vector<int64_t> ev_steps;  // steps covered by each recorded group of 5
     double prof_ms[4] = {0, 0, 0, 0};
     std::string err;
 };
@@ -238,9 +249,27 @@ int resolve_nlk(int64_t N, int n, int L, int k, int *Lo, int *ko, char *msg, siz
     return RBFSL_OK;
 }
 
+void ahead_free(rbfsl_ctx *c) {
+    void *bufs[] = {c->aex, c->aey, c->aez, c->as2, c->aw, c->aS, c->acidx, c->asc};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    c->aex = c->aey = c->aez = c->as2 = c->aw = nullptr;
+    c->aS = c->acidx = nullptr;
+    c->asc = nullptr;
+    for (int b = 0; b < 2; ++b) {
+        if (c->asc_host[b]) (void)hipHostFree(c->asc_host[b]);
+        if (c->asc_done[b]) (void)hipEventDestroy(c->asc_done[b]);
+        c->asc_host[b] = nullptr;
+        c->asc_done[b] = nullptr;
+        c->asc_used[b] = false;
+    }
+    c->ahead_cap = 0;
+}
+
 void ctx_free(rbfsl_ctx *c) {
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     c->ev.clear();
+    ahead_free(c);
     void *bufs[] = {c->nx, c->ny, c->nz, c->ex, c->ey, c->ez, c->S, c->s2, c->cidx, c->w,
                     c->q[0], c->q[1], c->status, c->F, c->frinv, c->fpiv, c->fstep, c->fstat,
                     c->cx, c->cy, c->cz, c->pd2, c->pr2, c->coef, c->sd2, c->sval, c->ploc, c->pidx, c->pcnt, c->sidx};
@@ -272,7 +301,7 @@ hipError_t prof_mark(rbfsl_ctx *c, int phase) {
         if (r != hipSuccess) return r;
         c->ev.push_back(e);
     }
-    (void)phase;
+    if (phase == 4) c->ev_steps.push_back(1);
     return hipEventRecord(c->ev[c->ev_used++], c->stream);
 }
 
@@ -283,9 +312,11 @@ void prof_collect(rbfsl_ctx *c) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, c->ev[b + ph], c->ev[b + ph + 1]) == hipSuccess) c->prof_ms[ph] += ms;
         }
-        c->prof_steps += 1;
+        const size_t gi = (size_t)(b / 5);
+        c->prof_steps += (gi < c->ev_steps.size()) ? c->ev_steps[gi] : 1;
     }
     c->ev_used = 0;
+    c->ev_steps.clear();
 }
 
 PuArgs pu_args(const rbfsl_ctx *c, int64_t m) {
@@ -356,6 +387,121 @@ hipError_t enqueue_step(rbfsl_ctx *c, int64_t m) {
                      c->q[c->cur], c->q[1 - c->cur], c->status, m, c->stream);
     if (e != hipSuccess) return e;
     return prof_mark(c, 4);
+}
+
+// Runs of small problems take several steps per launch: the departure points,
+// stencils and weights of a step do not depend on the transported field (the
+// velocity is prescribed), so K steps' tracer, search and solve run as one
+// launch each, and then the K field updates in step order.  Every step's
+// arithmetic is the step-by-step path's.
+constexpr int64_t AHEAD_STENCILS = 131072;  // stencils per launch aimed at
+constexpr int64_t AHEAD_MAX = 128;
+
+int64_t ahead_steps(const rbfsl_ctx *c, int64_t nsteps) {
+    if (c->mode == RBFSL_STENCIL_PU || c->cached || nsteps < 2) return 1;
+    int64_t K = AHEAD_STENCILS / c->N;
+    if (K > AHEAD_MAX) K = AHEAD_MAX;
+    if (K > nsteps) K = nsteps;
+    return (K < 2) ? 1 : K;
+}
+
+hipError_t ahead_alloc(rbfsl_ctx *c, int64_t K) {
+    if (K <= c->ahead_cap) return hipSuccess;
+    ahead_free(c);
+    const int64_t KN = K * c->N;
+    hipError_t e = hipSuccess;
+#define ALLOC(ptr, bytes) if (e == hipSuccess) e = hipMalloc(&(ptr), (bytes))
+    ALLOC(c->aex, sizeof(double) * KN);
+    ALLOC(c->aey, sizeof(double) * KN);
+    ALLOC(c->aez, sizeof(double) * KN);
+    ALLOC(c->aw, sizeof(double) * KN * c->n);
+    if (c->mode == 0) {
+        ALLOC(c->as2, sizeof(double) * KN);
+        ALLOC(c->aS, sizeof(int32_t) * KN * c->n);
+    } else {
+        ALLOC(c->acidx, sizeof(int32_t) * KN);
+    }
+    ALLOC(c->asc, sizeof(StepCoef) * K);
+#undef ALLOC
+    for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+        e = hipHostMalloc((void **)&c->asc_host[b], sizeof(StepCoef) * K, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->asc_done[b], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+        ahead_free(c);
+        return e;
+    }
+    c->ahead_cap = K;
+    return hipSuccess;
+}
+
+// steps m .. m + K - 1; q^m is in q[par]; chunk parity cb selects the staging
+hipError_t enqueue_steps(rbfsl_ctx *c, int64_t m, int K, int par, int cb) {
+    hipError_t e;
+    if (c->asc_used[cb] && (e = hipEventSynchronize(c->asc_done[cb])) != hipSuccess) return e;
+    for (int s = 0; s < K; ++s) c->asc_host[cb][s] = make_step_coef(c->p, m + s);
+    if ((e = hipMemcpyAsync(c->asc, c->asc_host[cb], sizeof(StepCoef) * K, hipMemcpyHostToDevice, c->stream)) !=
+        hipSuccess)
+        return e;
+    if ((e = hipEventRecord(c->asc_done[cb], c->stream)) != hipSuccess) return e;
+    c->asc_used[cb] = true;
+    const int64_t N = c->N, KN = (int64_t)K * N;
+    if ((e = prof_mark(c, 0)) != hipSuccess) return e;
+    if ((e = launch_trace_steps(c->nx, c->ny, c->nz, N, c->asc, K, c->aex, c->aey, c->aez, c->status, m,
+                                c->stream)) != hipSuccess)
+        return e;
+    if ((e = prof_mark(c, 1)) != hipSuccess) return e;
+    if (c->mode == 0)
+        e = launch_knn(c->grid, N, c->aex, c->aey, c->aez, KN, c->n, c->aS, nullptr, c->as2, c->status, m, c->stream, N);
+    else
+        e = launch_knn(c->grid, N, c->aex, c->aey, c->aez, KN, 1, c->acidx, nullptr, nullptr, c->status, m, c->stream, N);
+    if (e != hipSuccess) return e;
+    if ((e = prof_mark(c, 2)) != hipSuccess) return e;
+    SolveArgs a{};
+    a.nx = c->nx; a.ny = c->ny; a.nz = c->nz; a.N = N;
+    a.ex = c->aex; a.ey = c->aey; a.ez = c->aez;
+    if (c->mode == 1) {
+        a.cx = c->nx; a.cy = c->ny; a.cz = c->nz;
+        a.cidx = c->acidx;
+        a.S = c->S; a.s2 = c->s2;
+    } else {
+        a.S = c->aS; a.s2 = c->as2;
+    }
+    a.count = KN; a.n = c->n; a.L = c->L; a.k = c->k;
+    a.w = c->aw; a.st_out = nullptr; a.status = c->status; a.step = m; a.step_count = N;
+    if ((e = launch_solve(a, c->stream)) != hipSuccess) return e;
+    if ((e = prof_mark(c, 3)) != hipSuccess) return e;
+    // the K field updates, one launch each (one workgroup holding the field
+    // in LDS across the steps measured 3x slower at N = 1,024: a single
+    // compute unit cannot stream the steps' weights fast enough)
+    const int32_t *Sb = (c->mode == 0) ? c->aS : c->S;
+    const int64_t sstride = (c->mode == 0) ? N * c->n : 0;
+    for (int s = 0; s < K && e == hipSuccess; ++s)
+        e = launch_apply(c->aw + (int64_t)s * N * c->n, Sb + s * sstride,
+                         (c->mode == 1) ? c->acidx + s * N : nullptr, N, c->n, c->ntr, c->q[par ^ (s & 1)],
+                         c->q[par ^ ((s + 1) & 1)], c->status, m + s, c->stream);
+    if (e != hipSuccess) return e;
+    if ((e = prof_mark(c, 4)) != hipSuccess) return e;
+    if (c->prof && !c->ev_steps.empty()) c->ev_steps.back() = K;
+    return hipSuccess;
+}
+
+// the last step's departure points, stencils and weights to the single-step
+// buffers (what the debug taps read)
+hipError_t ahead_publish(rbfsl_ctx *c, int s) {
+    const int64_t N = c->N, n = c->n;
+    const hipMemcpyKind k = hipMemcpyDeviceToDevice;
+    hipError_t e = hipMemcpyAsync(c->ex, c->aex + s * N, sizeof(double) * N, k, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->ey, c->aey + s * N, sizeof(double) * N, k, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->ez, c->aez + s * N, sizeof(double) * N, k, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->w, c->aw + s * N * n, sizeof(double) * N * n, k, c->stream);
+    if (c->mode == 0) {
+        if (e == hipSuccess) e = hipMemcpyAsync(c->S, c->aS + s * N * n, sizeof(int32_t) * N * n, k, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(c->s2, c->as2 + s * N, sizeof(double) * N, k, c->stream);
+    } else {
+        if (e == hipSuccess) e = hipMemcpyAsync(c->cidx, c->acidx + s * N, sizeof(int32_t) * N, k, c->stream);
+    }
+    return e;
 }
 
 }  // namespace
@@ -642,13 +788,31 @@ int rbfsl_run(rbfsl_ctx *c, int64_t nsteps) {
     HIP_TRY(c, launch_status_reset(c->status, c->stream));
     const int64_t m0 = c->step;
     const int cur0 = c->cur;
-    for (int64_t m = m0; m < m0 + nsteps; ++m) {
-        c->cur = cur0 ^ (int)((m - m0) & 1);  // buffer holding q^m
-        hipError_t e = enqueue_step(c, m);
-        if (e != hipSuccess) {
-            (void)hipStreamSynchronize(c->stream);
-            c->cur = cur0;
-            return fail(c, RBFSL_E_DEVICE, "step %lld launch: %s", (long long)m, hipGetErrorString(e));
+    const int64_t K = ahead_steps(c, nsteps);
+    if (K > 1) {
+        HIP_TRY(c, ahead_alloc(c, K));
+        int cb = 0;
+        int64_t last = 0;
+        for (int64_t m = m0; m < m0 + nsteps; m += K, cb ^= 1) {
+            const int Kc = (int)std::min<int64_t>(K, m0 + nsteps - m);
+            hipError_t e = enqueue_steps(c, m, Kc, cur0 ^ (int)((m - m0) & 1), cb);
+            if (e != hipSuccess) {
+                (void)hipStreamSynchronize(c->stream);
+                c->cur = cur0;
+                return fail(c, RBFSL_E_DEVICE, "steps %lld.. launch: %s", (long long)m, hipGetErrorString(e));
+            }
+            last = Kc - 1;
+        }
+        HIP_TRY(c, ahead_publish(c, (int)last));
+    } else {
+        for (int64_t m = m0; m < m0 + nsteps; ++m) {
+            c->cur = cur0 ^ (int)((m - m0) & 1);  // buffer holding q^m
+            hipError_t e = enqueue_step(c, m);
+            if (e != hipSuccess) {
+                (void)hipStreamSynchronize(c->stream);
+                c->cur = cur0;
+                return fail(c, RBFSL_E_DEVICE, "step %lld launch: %s", (long long)m, hipGetErrorString(e));
+            }
         }
     }
     int st[ST_WORDS];
@@ -676,6 +840,11 @@ int rbfsl_run(rbfsl_ctx *c, int64_t nsteps) {
 }
 
 int rbfsl_step(rbfsl_ctx *c) { return rbfsl_run(c, 1); }
+
+int64_t rbfsl_steps_per_launch(const rbfsl_ctx *c, int64_t nsteps) {
+    if (!c || nsteps < 1) return 1;
+    return ahead_steps(c, nsteps);
+}
 
 int rbfsl_get_q(rbfsl_ctx *c, double *out, int on_device) {
     if (!c || !out) return RBFSL_E_INVAL;

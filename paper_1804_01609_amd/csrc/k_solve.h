@@ -194,19 +194,18 @@ __device__ __forceinline__ double wave_max_nonneg(double v) {
 }
 
 
-// Assembly of one system (eq. rbf_poly_linsys in the local graded basis):
-// this lane's rows (i = lane + 64 r) of this wave's columns go to a, the
-// right-hand side [b; p(xi)] of the same rows to y.  stage holds the local
-// coordinates and basis tables; one barrier between filling and reading them.
-template <int W, int R, int NCB, int B, int CM = 24>
-__device__ __forceinline__ void assemble_system(double *const stage, const int t, const SysIn &A,
-                                                double (&a)[R][Cfg<W, R, NCB, B, 1, CM>::NC], double (&y)[R]) {
-    using C = Cfg<W, R, NCB, B, 1, CM>;
-    constexpr int NT = C::NT, MCAP = C::MCAP, NC = C::NC;
-    const int lane = t & 63, wv = t >> 6;
-    const int n = A.n, L = A.L, k = A.k;
+// Assembly tables of one system (eq. rbf_poly_linsys in the local graded
+// basis): the scaled local coordinates of the stencil nodes (3 x MCAP), the
+// evaluation point's (3) and its basis values, and the n x mL basis values of
+// the nodes, all in stage; NT threads; the caller puts a barrier between
+// filling and reading them.
+struct SysTables {
+    const double *yb, *yxb, *peb, *Pb;
+};
+template <int NT, int MCAP>
+__device__ __forceinline__ SysTables assembly_tables(double *const stage, const int t, const SysIn &A) {
+    const int n = A.n, L = A.L;
     const int mL = (L + 1) * (L + 1);
-    const int M = n + mL;
 
     // ---- stencil, centre, scale, frame ----
     const int32_t *Srow = A.S;
@@ -218,7 +217,6 @@ __device__ __forceinline__ void assemble_system(double *const stage, const int t
     double e1[3], e2[3];
     frame3(ctr, e1, e2);
 
-    // ---- assembly 1: local coordinates and basis tables ----
     double *yb = stage;                 // 3 x MCAP scaled local coordinates
     double *yxb = stage + 3 * MCAP;     // evaluation point (3) ...
     double *peb = yxb + 4;              // ... and its basis values (mL <= MCAP)
@@ -246,38 +244,64 @@ __device__ __forceinline__ void assemble_system(double *const stage, const int t
             basis_all(L, al, be, u, peb);
         }
     }
-    __syncthreads();
+    return SysTables{yb, yxb, peb, Pb};
+}
 
-    // ---- assembly 2: my rows, my columns; the right-hand side ----
-    const double yx0 = yxb[0], yx1 = yxb[1], yx2 = yxb[2];
+// Entry (i, jc) of the saddle-point matrix, i a row below M whose scaled
+// local coordinates are yi (rows i >= n: any); 0 outside M x M
+__device__ __forceinline__ double system_entry(const SysTables &tb, int i, int jc, double yi0, double yi1,
+                                               double yi2, int n, int M, int mL, int k) {
+    double v = 0.0;
+    if (i < n) {
+        if (jc < n) {
+            double d0 = yi0 - tb.yb[3 * jc], d1 = yi1 - tb.yb[3 * jc + 1], d2 = yi2 - tb.yb[3 * jc + 2];
+            v = phs((d0 * d0 + d1 * d1) + d2 * d2, k);
+        } else if (jc < M) {
+            v = tb.Pb[i * mL + (jc - n)];
+        }
+    } else if (i < M) {
+        if (jc < n) v = tb.Pb[jc * mL + (i - n)];
+    }
+    return v;
+}
+
+// Entry i of the right-hand side [b; p(xi)]: the kernel between node i and the
+// evaluation point, or the evaluation point's basis value i - n; 0 from M on
+__device__ __forceinline__ double system_rhs(const SysTables &tb, int i, double yi0, double yi1, double yi2, int n,
+                                             int M, int k) {
+    double rhs = 0.0;
+    if (i < n) {
+        double d0 = yi0 - tb.yxb[0], d1 = yi1 - tb.yxb[1], d2 = yi2 - tb.yxb[2];
+        rhs = phs((d0 * d0 + d1 * d1) + d2 * d2, k);
+    } else if (i < M) {
+        rhs = tb.peb[i - n];
+    }
+    return rhs;
+}
+
+// Assembly of one system: this lane's rows (i = lane + 64 r) of this wave's
+// columns go to a, the right-hand side of the same rows to y.
+template <int W, int R, int NCB, int B, int CM = 24>
+__device__ __forceinline__ void assemble_system(double *const stage, const int t, const SysIn &A,
+                                                double (&a)[R][Cfg<W, R, NCB, B, 1, CM>::NC], double (&y)[R]) {
+    using C = Cfg<W, R, NCB, B, 1, CM>;
+    constexpr int NT = C::NT, MCAP = C::MCAP, NC = C::NC;
+    const int lane = t & 63, wv = t >> 6;
+    const int n = A.n, L = A.L, k = A.k;
+    const int mL = (L + 1) * (L + 1);
+    const int M = n + mL;
+    const SysTables tb = assembly_tables<NT, MCAP>(stage, t, A);
+    __syncthreads();
     sfor<0, R>([&](auto RI) SI {
         constexpr int r = RI;
         const int i = lane + 64 * r;
         double yi0 = 0.0, yi1 = 0.0, yi2 = 0.0;
-        if (i < n) { yi0 = yb[3 * i]; yi1 = yb[3 * i + 1]; yi2 = yb[3 * i + 2]; }
-        double rhs = 0.0;
-        if (i < n) {
-            double d0 = yi0 - yx0, d1 = yi1 - yx1, d2 = yi2 - yx2;
-            rhs = phs((d0 * d0 + d1 * d1) + d2 * d2, k);
-        } else if (i < M) {
-            rhs = peb[i - n];
-        }
-        y[r] = rhs;
+        if (i < n) { yi0 = tb.yb[3 * i]; yi1 = tb.yb[3 * i + 1]; yi2 = tb.yb[3 * i + 2]; }
+        y[r] = system_rhs(tb, i, yi0, yi1, yi2, n, M, k);
         sfor<0, NC>([&](auto S) SI {
             constexpr int sl = S;
             const int jc = ((sl / B) * W + wv) * B + sl % B;
-            double v = 0.0;
-            if (i < n) {
-                if (jc < n) {
-                    double d0 = yi0 - yb[3 * jc], d1 = yi1 - yb[3 * jc + 1], d2 = yi2 - yb[3 * jc + 2];
-                    v = phs((d0 * d0 + d1 * d1) + d2 * d2, k);
-                } else if (jc < M) {
-                    v = Pb[i * mL + (jc - n)];
-                }
-            } else if (i < M) {
-                if (jc < n) v = Pb[jc * mL + (i - n)];
-            }
-            a[r][sl] = v;
+            a[r][sl] = system_entry(tb, i, jc, yi0, yi1, yi2, n, M, mL, k);
         });
     });
 }
@@ -606,8 +630,9 @@ __attribute__((amdgpu_waves_per_eu(WPE, WPE))) k_solve(SolveArgs A) {
     const int64_t j = blockIdx.x;
     const int t = threadIdx.x;
     constexpr int NT = 64 * W;
+    const int64_t step = A.step + (A.step_count ? j / A.step_count : 0);
     // one read for the whole workgroup: this or an earlier step already failed
-    if (t == 0) skip = (A.status[ST_FAILSTEP] <= A.step);
+    if (t == 0) skip = (A.status[ST_FAILSTEP] <= step);
     __syncthreads();
     if (skip) return;
     const int n = A.n;
@@ -623,11 +648,11 @@ __attribute__((amdgpu_waves_per_eu(WPE, WPE))) k_solve(SolveArgs A) {
     }
     in.s2 = A.s2[row];
     in.n = n; in.L = A.L; in.k = A.k;
-    in.status = A.status; in.step = A.step;
+    in.status = A.status; in.step = step;
     if (!solve_system<W, R, NCB, B, false>(sh, t, in)) {
         if (t == 0) {
             atomicAdd(&A.status[ST_SINGULAR], 1);
-            atomicMin(&A.status[ST_FAILSTEP], (int)A.step);
+            atomicMin(&A.status[ST_FAILSTEP], (int)step);
             if (A.st_out) A.st_out[j] = RBFSL_E_SINGULAR;
         }
         return;
@@ -643,7 +668,7 @@ __attribute__((amdgpu_waves_per_eu(WPE, WPE))) k_solve(SolveArgs A) {
     if (t == 0) {
         if (anybad) {
             atomicAdd(&A.status[ST_NONFINITE], 1);
-            atomicMin(&A.status[ST_FAILSTEP], (int)A.step);
+            atomicMin(&A.status[ST_FAILSTEP], (int)step);
         }
         if (A.st_out) A.st_out[j] = anybad ? RBFSL_E_NONFINITE : 0;
     }

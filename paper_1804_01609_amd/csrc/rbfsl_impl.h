@@ -70,6 +70,11 @@ constexpr int MAX_SYSTEM = 192;
 hipError_t launch_trace(const double *nx, const double *ny, const double *nz, int64_t N,
                         const StepCoef &sc, double *ex, double *ey, double *ez,
                         const int *status, int64_t step, hipStream_t s);
+// the departure points of steps m0 .. m0 + K - 1 (sc: K device coefficients),
+// step s's to ex[s N ..]
+hipError_t launch_trace_steps(const double *nx, const double *ny, const double *nz, int64_t N,
+                              const StepCoef *sc, int K, double *ex, double *ey, double *ez,
+                              const int *status, int64_t m0, hipStream_t s);
 
 hipError_t grid_build(const double *nx, const double *ny, const double *nz, int64_t N, int n,
                       Grid *g, hipStream_t s);
@@ -85,7 +90,8 @@ void grid_free(Grid *g);
 // null; s2: Q (squared distance of the n-th neighbour) or null.
 hipError_t launch_knn(const Grid &g, int64_t N, const double *qx, const double *qy,
                       const double *qz, int64_t Q, int n, int32_t *idx, double *d2, double *s2,
-                      int *status, int64_t step, hipStream_t s);
+                      int *status, int64_t step, hipStream_t s, int64_t per = 0);
+// (per > 0: the queries of consecutive steps step, step + 1, ..., per each)
 
 // Weights of `count` stencils.  Stencil t uses node indices S[row(t)*n..],
 // squared scale s2[row(t)], centre c[row(t)] (or its own evaluation point when
@@ -104,6 +110,7 @@ struct SolveArgs {
     int32_t *st_out;             // optional per-stencil status
     int *status;
     int64_t step;
+    int64_t step_count;          // > 0: stencils of consecutive steps, step_count per step
     // factor-only use with stencils of different sizes (RBF-PU patches):
     // stencil t has nvar[row(t)] <= n nodes, stored with row stride sstride
     // (null / 0: every stencil has n nodes, stride n)
@@ -196,7 +203,6 @@ hipError_t launch_pu_eval(const PuArgs &a, hipStream_t s);
 hipError_t launch_apply(const double *w, const int32_t *S, const int32_t *cidx, int64_t N, int n,
                         int ntr, const double *qin, double *qout, const int *status,
                         int64_t step, hipStream_t s);
-
 hipError_t launch_status_reset(int *status, hipStream_t s);
 
 // ---- host helpers shared by the single-run and the pooled API (api.hip) ----
