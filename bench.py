@@ -277,7 +277,10 @@ def main():
             f"({out['batched']['speedup_vs_plain']:.3f}x the plain path)")
     if "served" in sections:
         out["served"] = bench_served(args.served_requests, args.served_load, args.served_step_scale)
-        say(f"served: p50 {out['served']['p50_s']:.2f} s, p99 {out['served']['p99_s']:.2f} s")
+        sv = out["served"]
+        say(f"served: p50 {sv['p50_s']:.2f} s, p99 {sv['p99_s']:.2f} s (single-run FIFO on the same arrivals: "
+            f"p50 {sv['plain_fifo']['p50_s']:.2f} s, p99 {sv['plain_fifo']['p99_s']:.2f} s; results equal: "
+            f"{sv['plain_fifo']['results_equal_pool']})")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, X, q0, args.cpu_seconds)
     print(json.dumps(out), flush=True)
@@ -438,18 +441,42 @@ def bench_served(nreq, load, step_scale):
     for r in reqs:
         X, p = _run_inputs(r)
         items.append(dict(arrival=r["arrival"], nodes=X, params=p, q0=W.request_q0(r, X), nsteps=r["nsteps"]))
-    with rb.Pool(max_runs=64, hbm_budget=200 * 10 ** 9) as pl:
+    with rb.Pool(max_runs=64, hbm_budget=200 * 10 ** 9, log_requests=True) as pl:
         res, outs, wall = pl.serve(items)
     lat = np.array([x["finished"] - it["arrival"] for x, it in zip(res, items)])
     ok = all(x["status"] == rb.RBFSL_OK for x in res)
     total = sum(it["nodes"].shape[0] * it["nsteps"] for it in items)
+    # the same requests on the single-run path, one after another in arrival
+    # order (a first-come first-served server): each request's device run time
+    # (context creation and the copies excluded), the latencies such a server
+    # would give on the same arrivals, and the results, which must be the pool's
+    plain_s, same = [], True
+    for it, out in zip(items, outs):
+        tr = rb.Transport(it["nodes"], it["params"])
+        tr.set_q(it["q0"])
+        tr.get_q()  # the upload has landed
+        t0 = time.perf_counter()
+        tr.run(it["nsteps"])  # returns once the run is complete
+        plain_s.append(time.perf_counter() - t0)
+        say(f"served, single-run path: request {len(plain_s) - 1} took {plain_s[-1]:.2f} s")
+        same = same and np.array_equal(tr.get_q(), out)
+        tr.close()
+    free_at, plain_lat = 0.0, []
+    for it, d in zip(items, plain_s):
+        start = max(free_at, it["arrival"])
+        free_at = start + d
+        plain_lat.append(free_at - it["arrival"])
+    plain_lat = np.array(plain_lat)
     return {"workload": f"c5-served-{nreq}req-N4096..262144-(31,3,2)/(56,4,2)/(84,5,3)/(120,7,4)"
                         f"-steps{smin}..{smax}-seed1",
             "requests": nreq, "load": load, "rate_per_s": rate, "mean_request_device_s": sec,
             "calibration_ns_per_interp": {f"{n},{L},{k}": v for (n, L, k), v in cal.items()},
             "all_ok": ok, "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
             "mean_s": float(lat.mean()), "wall_s": wall,
-            "value": total / wall, "unit": "interpolations/s", "hbm_budget_bytes": 200 * 10 ** 9}
+            "value": total / wall, "unit": "interpolations/s", "hbm_budget_bytes": 200 * 10 ** 9,
+            "plain_fifo": {"p50_s": float(np.percentile(plain_lat, 50)), "p99_s": float(np.percentile(plain_lat, 99)),
+                           "mean_s": float(plain_lat.mean()), "busy_s": float(sum(plain_s)),
+                           "interp_per_s_busy": total / sum(plain_s), "results_equal_pool": bool(same)}}
 
 
 if __name__ == "__main__":

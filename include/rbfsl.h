@@ -279,6 +279,9 @@ typedef struct {
     int32_t use_graph;  /* 1: every step is one replay of a captured HIP graph;   *
                          * 0: the same kernels launched one by one                */
     int64_t hbm_budget; /* bytes reserved for run state; 0: half the free memory  */
+    int32_t log_requests; /* 1: rbfsl_pool_serve writes one line per completed    *
+                           * request to stderr (index, time, status)              */
+    int32_t reserved;     /* 0                                                    */
 } rbfsl_pool_config;
 
 int rbfsl_pool_create(const rbfsl_pool_config *cfg, rbfsl_pool **out);

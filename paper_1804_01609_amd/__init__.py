@@ -61,7 +61,8 @@ class Params(ctypes.Structure):
 
 
 class PoolConfig(ctypes.Structure):
-    _fields_ = [("max_runs", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("hbm_budget", ctypes.c_int64)]
+    _fields_ = [("max_runs", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("hbm_budget", ctypes.c_int64),
+                ("log_requests", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class PoolStats(ctypes.Structure):
@@ -459,8 +460,8 @@ class Pool:
     """Many independent runs resident on the GPU and stepped together
     (batched form), or fed by a request stream (served form)."""
 
-    def __init__(self, max_runs=64, hbm_budget=0, use_graph=True):
-        cfg = PoolConfig(int(max_runs), int(bool(use_graph)), int(hbm_budget))
+    def __init__(self, max_runs=64, hbm_budget=0, use_graph=True, log_requests=False):
+        cfg = PoolConfig(int(max_runs), int(bool(use_graph)), int(hbm_budget), int(bool(log_requests)), 0)
         self._p = _P()
         code = lib().rbfsl_pool_create(ctypes.byref(cfg), ctypes.byref(self._p))
         if code != RBFSL_OK:

@@ -197,6 +197,7 @@ struct rbfsl_pool {
     bool admit_pending = false;
     int max_runs = 0;
     bool use_graph = true;
+    bool log_requests = false;
     Arena arena;
     std::vector<Run> runs;
     int64_t next_id = 0;
@@ -590,6 +591,7 @@ int rbfsl_pool_create(const rbfsl_pool_config *cfg, rbfsl_pool **out) {
     if (!pl) return RBFSL_E_NOMEM;
     pl->max_runs = cfg->max_runs;
     pl->use_graph = cfg->use_graph != 0;
+    pl->log_requests = cfg->log_requests != 0;
     pl->runs.assign((size_t)pl->max_runs, Run());
     hipError_t e = hipGetDevice(&pl->device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&pl->ncu, hipDeviceAttributeMultiprocessorCount, pl->device);
@@ -861,6 +863,9 @@ int rbfsl_pool_serve(rbfsl_pool *pl, const rbfsl_request *req, int64_t nreq, rbf
         res[i].finished = now_s() - tnow;
         req_of.erase(r.id);
         ++done;
+        if (pl->log_requests)
+            fprintf(stderr, "serve: request %lld done at %.2f s (%lld of %lld), status %d, %lld steps\n", (long long)i,
+                    res[i].finished, (long long)done, (long long)nreq, res[i].status, (long long)res[i].steps);
         return release_run(pl, slot);
     };
     while (done < nreq && rc == RBFSL_OK) {
