@@ -70,6 +70,7 @@ struct SolveSmem {
     double rinvb[C::MCAP];
     double zb[C::MCAP];   // the solution; its first n entries are the weights
     int pivb[C::MCAP];
+    int stepb[C::ROWS];   // the step at which each row was the pivot row (16-wave layout)
     int failk[2];         // failing step of a panel, by block parity
 };
 
@@ -406,6 +407,10 @@ __device__ __forceinline__ bool solve_system(SolveSmem<W, R, NCB, B, CM> &sh, co
                                              const FactorOut *fo = nullptr) {
     using C = Cfg<W, R, NCB, B, 1, CM>;
     constexpr int NT = C::NT, ROWS = C::ROWS, MCAP = C::MCAP, NC = C::NC;
+    // the 16-wave layout (M <= 192) records each row's pivot step once after
+    // the elimination instead of in every wave at every step (1% of its time;
+    // the layouts near their register limit keep the per-step form)
+    constexpr bool LATE = (R >= 3 && W >= 16);
     double *const stage = sh.stage;
     double *const rinvb = sh.rinvb;
     double *const zb = sh.zb;
@@ -481,7 +486,7 @@ __device__ __forceinline__ bool solve_system(SolveSmem<W, R, NCB, B, CM> &sh, co
             double l[R];
             sfor<0, R>([&](auto RI) SI {
                 constexpr int r = RI;
-                if (pr == r && lane == pl) { used[r] = true; stepof[r] = kk; }
+                if (pr == r && lane == pl) { used[r] = true; if constexpr (!LATE) stepof[r] = kk; }
                 l[r] = used[r] ? 0.0 : a[r][ps0 + c] * rinv;
                 lb[g & 1][c][lane + 64 * r] = l[r];
             });
@@ -520,7 +525,7 @@ __device__ __forceinline__ bool solve_system(SolveSmem<W, R, NCB, B, CM> &sh, co
             sfor<0, R>([&](auto RI) SI { l[RI] = lb[g & 1][c][lane + 64 * RI]; });
             sfor<0, R>([&](auto RI) SI {
                 constexpr int r = RI;
-                if (pr == r && lane == pl) { used[r] = true; stepof[r] = kk; }
+                if (pr == r && lane == pl) { used[r] = true; if constexpr (!LATE) stepof[r] = kk; }
             });
             sfor<0, R>([&](auto PRI) SI {
                 constexpr int prr = PRI;
@@ -571,6 +576,14 @@ __device__ __forceinline__ bool solve_system(SolveSmem<W, R, NCB, B, CM> &sh, co
         }
     });
     if (!LOCK && dead) return false;
+    if constexpr (LATE) {  // the step at which each row was pivoted, from the pivot list
+        int *const stepb = sh.stepb;
+        for (int i = t; i < C::ROWS; i += NT) stepb[i] = MCAP;
+        __syncthreads();
+        for (int kk = t; kk < M; kk += NT) stepb[pivb[kk]] = kk;
+        __syncthreads();
+        sfor<0, R>([&](auto RI) SI { stepof[RI] = stepb[lane + 64 * RI]; });
+    }
 
     if constexpr (FACT) {
         // factor-only mode: store the factorization instead of solving
