@@ -92,16 +92,17 @@ def solver_sources_sha256(M):
     return h.hexdigest()
 
 
-def measured_traffic(cfg, M):
+def measured_traffic(cfg, M, spl):
     """HBM bytes per k_solve launch from the committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE, each scaled by a known-size copy kernel), or None
-    when the summary is missing or the solver sources changed since it was taken."""
+    when the summary is missing, the solver sources changed since it was taken,
+    or its launches covered another number of steps than `spl`."""
     key = cfg["name"].split("-")[0]
     path = os.path.join(ROOT, "profiles", f"k_solve_{key}_N{cfg['N']}_M{M}_counters.txt")
     if not os.path.exists(path):
         return None
     kv = dict(line.strip().split("=", 1) for line in open(path) if "=" in line and not line.startswith("#"))
-    if kv.get("source_sha256") != solver_sources_sha256(M):
+    if kv.get("source_sha256") != solver_sources_sha256(M) or int(kv.get("steps_per_launch", 1)) != spl:
         return None
     return float(kv["hbm_bytes_per_launch"])
 
@@ -183,7 +184,7 @@ def bench_plain(name, steps, warmup, sync):
         "phase_ms_per_step": {nm: phase_ms[i] / max(nrec, 1) for i, nm in enumerate(["trace", "knn", "solve", "apply"])},
         "roofline": {"kernel": "k_solve", "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                     "traffic": measured_traffic(cfg, M), "traffic_unit": "bytes/launch",
+                     "traffic": measured_traffic(cfg, M, spl), "traffic_unit": "bytes/launch",
                      "flops_per_launch": fl * spl, "flops_per_stencil": stencil_flops(n, L, k),
                      "launch_ms": solve_ms * spl, "steps_per_launch": spl},
     }, X, q0

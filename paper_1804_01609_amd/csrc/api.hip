@@ -43,25 +43,39 @@ struct rbfsl_ctx {
     Grid cgrid;
     double *q[2] = {nullptr, nullptr};
     int cur = 0;
-    // several steps per launch (runs of small problems): departure points,
-    // stencils and weights of up to ahead_cap steps, their tracer
-    // coefficients (device, and pinned staging by chunk parity)
+    // several steps per launch (runs of small problems): two sets, by chunk
+    // parity, of the departure points, stencils and weights of up to
+    // ahead_cap steps with their tracer coefficients (device, and pinned
+    // staging).  The tracer, search and solve of a chunk run on wstream while
+    // the field updates of the previous chunk run on the context's stream.
+    struct AheadSet {
+        double *ex = nullptr, *ey = nullptr, *ez = nullptr, *s2 = nullptr, *w = nullptr;
+        int32_t *S = nullptr, *cidx = nullptr;
+        StepCoef *sc = nullptr, *sc_host = nullptr;
+        const StepCoef *sc_mapped = nullptr;  // sc_host's device address
+        hipEvent_t staged = nullptr;   // the coefficients' staging has run
+        hipEvent_t solved = nullptr;   // the chunk's weights are written
+        hipEvent_t applied = nullptr;  // the chunk's field updates have run
+        bool used = false;
+    };
     int64_t ahead_cap = 0;
-    double *aex = nullptr, *aey = nullptr, *aez = nullptr, *as2 = nullptr, *aw = nullptr;
-    int32_t *aS = nullptr, *acidx = nullptr;
-    StepCoef *asc = nullptr;
-    StepCoef *asc_host[2] = {nullptr, nullptr};
-    hipEvent_t asc_done[2] = {nullptr, nullptr};
-    bool asc_used[2] = {false, false};
+    AheadSet aset[2];
+    hipStream_t wstream = nullptr;
+    hipEvent_t run_start = nullptr;
+    // what the debug taps read: the single-step buffers, or after a run of
+    // several steps per launch, its last step's slice of an ahead set
+    const double *tex = nullptr, *tey = nullptr, *tez = nullptr, *tw = nullptr;
+    const int32_t *tS = nullptr, *tcidx = nullptr;
     int *status = nullptr;
     int64_t step = 0;
     bool q_set = false, ran = false;
     int64_t f_sing = 0, f_nonf = 0, f_search = 0;
-    // profiling: per-step events around the four phases
+    // profiling: per-step events around the four phases (trace, search and
+    // solve back to back on one stream, the field update on its own pair)
     bool prof = false;
-    std::vector<hipEvent_t> ev;  // 5 per recorded step
+    std::vector<hipEvent_t> ev;  // 6 per recorded step
     int64_t ev_used = 0, prof_steps = 0;
-    std::vector<int64_t> ev_steps;  // steps covered by each recorded group of 5
+    std::vector<int64_t> ev_steps;  // steps covered by each recorded group of 6
     double prof_ms[4] = {0, 0, 0, 0};
     std::string err;
 };
@@ -161,6 +175,15 @@ __global__ void k_soa_to_aos(const double *x, const double *y, const double *z, 
     aos[3 * i + 2] = z[i];
 }
 
+// A chunk's tracer coefficients from pinned host memory to the device, read by
+// a kernel on the weights stream itself (a copy-engine transfer there cost
+// 15-80 us of hand-over between engines at every chunk): one 8-byte word per
+// thread, so that every read of host memory is in flight at once.
+__global__ void k_stage_words(const uint64_t *src, uint64_t *dst, int64_t nwords) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nwords) dst[i] = src[i];
+}
+
 __global__ void k_gather_rows(const int32_t *S, const int32_t *cidx, int64_t N, int n, int32_t *out) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N * n) return;
@@ -250,20 +273,26 @@ int resolve_nlk(int64_t N, int n, int L, int k, int *Lo, int *ko, char *msg, siz
 }
 
 void ahead_free(rbfsl_ctx *c) {
-    void *bufs[] = {c->aex, c->aey, c->aez, c->as2, c->aw, c->aS, c->acidx, c->asc};
-    for (void *b : bufs)
-        if (b) (void)hipFree(b);
-    c->aex = c->aey = c->aez = c->as2 = c->aw = nullptr;
-    c->aS = c->acidx = nullptr;
-    c->asc = nullptr;
-    for (int b = 0; b < 2; ++b) {
-        if (c->asc_host[b]) (void)hipHostFree(c->asc_host[b]);
-        if (c->asc_done[b]) (void)hipEventDestroy(c->asc_done[b]);
-        c->asc_host[b] = nullptr;
-        c->asc_done[b] = nullptr;
-        c->asc_used[b] = false;
+    for (rbfsl_ctx::AheadSet &A : c->aset) {
+        void *bufs[] = {A.ex, A.ey, A.ez, A.s2, A.w, A.S, A.cidx, A.sc};
+        for (void *b : bufs)
+            if (b) (void)hipFree(b);
+        if (A.sc_host) (void)hipHostFree(A.sc_host);
+        hipEvent_t evs[] = {A.staged, A.solved, A.applied};
+        for (hipEvent_t e : evs)
+            if (e) (void)hipEventDestroy(e);
+        A = rbfsl_ctx::AheadSet{};
     }
+    if (c->run_start) (void)hipEventDestroy(c->run_start);
+    if (c->wstream) (void)hipStreamDestroy(c->wstream);
+    c->run_start = nullptr;
+    c->wstream = nullptr;
     c->ahead_cap = 0;
+}
+
+void taps_single(rbfsl_ctx *c) {
+    c->tex = c->ex; c->tey = c->ey; c->tez = c->ez; c->tw = c->w;
+    c->tS = c->S; c->tcidx = c->cidx;
 }
 
 void ctx_free(rbfsl_ctx *c) {
@@ -292,27 +321,39 @@ int status_code(const int st[ST_WORDS]) {
     return RBFSL_OK;
 }
 
-hipError_t prof_mark(rbfsl_ctx *c, int phase) {
+// One group of six events per profiled step (or chunk of steps): marks 0..3
+// open the trace, search and solve phases and close the solve, 4 and 5
+// bracket the field update.  prof_group reserves a group (-1 when not
+// profiling); prof_mark records one of its marks on stream s.
+hipError_t prof_group(rbfsl_ctx *c, int64_t steps, int64_t *g) {
+    *g = -1;
     if (!c->prof) return hipSuccess;
-    const int64_t need = c->ev_used + 1;
+    const int64_t need = c->ev_used + 6;
     while ((int64_t)c->ev.size() < need) {
         hipEvent_t e;
         hipError_t r = hipEventCreate(&e);
         if (r != hipSuccess) return r;
         c->ev.push_back(e);
     }
-    if (phase == 4) c->ev_steps.push_back(1);
-    return hipEventRecord(c->ev[c->ev_used++], c->stream);
+    *g = c->ev_used;
+    c->ev_used += 6;
+    c->ev_steps.push_back(steps);
+    return hipSuccess;
 }
+hipError_t prof_mark(rbfsl_ctx *c, int64_t g, int mark, hipStream_t s) {
+    return (g < 0) ? hipSuccess : hipEventRecord(c->ev[g + mark], s);
+}
+hipError_t prof_mark(rbfsl_ctx *c, int64_t g, int mark) { return prof_mark(c, g, mark, c->stream); }
 
 // fold recorded events into the per-phase totals (after a synchronisation)
 void prof_collect(rbfsl_ctx *c) {
-    for (int64_t b = 0; b + 5 <= c->ev_used; b += 5) {
+    for (int64_t b = 0; b + 6 <= c->ev_used; b += 6) {
         for (int ph = 0; ph < 4; ++ph) {
             float ms = 0.f;
-            if (hipEventElapsedTime(&ms, c->ev[b + ph], c->ev[b + ph + 1]) == hipSuccess) c->prof_ms[ph] += ms;
+            const int64_t i0 = b + ph + (ph == 3);
+            if (hipEventElapsedTime(&ms, c->ev[i0], c->ev[i0 + 1]) == hipSuccess) c->prof_ms[ph] += ms;
         }
-        const size_t gi = (size_t)(b / 5);
+        const size_t gi = (size_t)(b / 6);
         c->prof_steps += (gi < c->ev_steps.size()) ? c->ev_steps[gi] : 1;
     }
     c->ev_used = 0;
@@ -337,28 +378,30 @@ PuArgs pu_args(const rbfsl_ctx *c, int64_t m) {
 
 hipError_t enqueue_step(rbfsl_ctx *c, int64_t m) {
     const StepCoef sc = make_step_coef(c->p, m);
-    hipError_t e = prof_mark(c, 0);
+    int64_t g;
+    hipError_t e = prof_group(c, 1, &g);
+    if (e == hipSuccess) e = prof_mark(c, g, 0);
     if (e != hipSuccess) return e;
     e = launch_trace(c->nx, c->ny, c->nz, c->N, sc, c->ex, c->ey, c->ez, c->status, m, c->stream);
     if (e != hipSuccess) return e;
-    if ((e = prof_mark(c, 1)) != hipSuccess) return e;
+    if ((e = prof_mark(c, g, 1)) != hipSuccess) return e;
     if (c->mode == RBFSL_STENCIL_PU) {
         // the patches containing each departure point, the patches'
         // coefficients, the partition-of-unity blend
         const PuArgs a = pu_args(c, m);
         if ((e = launch_pu_search(a, c->cgrid, c->stream)) != hipSuccess) return e;
-        if ((e = prof_mark(c, 2)) != hipSuccess) return e;
+        if ((e = prof_mark(c, g, 2)) != hipSuccess) return e;
         if ((e = launch_pu_coef(a, c->stream)) != hipSuccess) return e;
-        if ((e = prof_mark(c, 3)) != hipSuccess) return e;
+        if ((e = prof_mark(c, g, 3)) != hipSuccess || (e = prof_mark(c, g, 4)) != hipSuccess) return e;
         if ((e = launch_pu_eval(a, c->stream)) != hipSuccess) return e;
-        return prof_mark(c, 4);
+        return prof_mark(c, g, 5);
     }
     if (c->mode == 0)
         e = launch_knn(c->grid, c->N, c->ex, c->ey, c->ez, c->N, c->n, c->S, nullptr, c->s2, c->status, m, c->stream);
     else
         e = launch_knn(c->grid, c->N, c->ex, c->ey, c->ez, c->N, 1, c->cidx, nullptr, nullptr, c->status, m, c->stream);
     if (e != hipSuccess) return e;
-    if ((e = prof_mark(c, 2)) != hipSuccess) return e;
+    if ((e = prof_mark(c, g, 2)) != hipSuccess) return e;
     SolveArgs a{};
     a.nx = c->nx; a.ny = c->ny; a.nz = c->nz; a.N = c->N;
     a.ex = c->ex; a.ey = c->ey; a.ez = c->ez;
@@ -382,51 +425,65 @@ hipError_t enqueue_step(rbfsl_ctx *c, int64_t m) {
         e = launch_solve(a, c->stream);
     }
     if (e != hipSuccess) return e;
-    if ((e = prof_mark(c, 3)) != hipSuccess) return e;
+    if ((e = prof_mark(c, g, 3)) != hipSuccess || (e = prof_mark(c, g, 4)) != hipSuccess) return e;
     e = launch_apply(c->w, c->S, c->mode == 1 ? c->cidx : nullptr, c->N, c->n, c->ntr,
                      c->q[c->cur], c->q[1 - c->cur], c->status, m, c->stream);
     if (e != hipSuccess) return e;
-    return prof_mark(c, 4);
+    return prof_mark(c, g, 5);
 }
 
 // Runs of small problems take several steps per launch: the departure points,
 // stencils and weights of a step do not depend on the transported field (the
 // velocity is prescribed), so K steps' tracer, search and solve run as one
 // launch each, and then the K field updates in step order.  Every step's
-// arithmetic is the step-by-step path's.
-constexpr int64_t AHEAD_STENCILS = 131072;  // stencils per launch aimed at
+// arithmetic is the step-by-step path's.  A run is cut into about AHEAD_CHUNKS
+// chunks so that the weights of one chunk are computed while the field
+// updates of the one before run.
+constexpr int64_t AHEAD_STENCILS = 131072;  // stencils per launch at most
 constexpr int64_t AHEAD_MAX = 128;
+constexpr int64_t AHEAD_CHUNKS = 4;
 
-int64_t ahead_steps(const rbfsl_ctx *c, int64_t nsteps) {
-    if (c->mode == RBFSL_STENCIL_PU || c->cached || nsteps < 2) return 1;
-    int64_t K = AHEAD_STENCILS / c->N;
-    if (K > AHEAD_MAX) K = AHEAD_MAX;
-    if (K > nsteps) K = nsteps;
+// the most steps per launch this context takes (1: step by step only)
+int64_t ahead_max(const rbfsl_ctx *c) {
+    if (c->mode == RBFSL_STENCIL_PU || c->cached) return 1;
+    const int64_t K = std::min(AHEAD_MAX, AHEAD_STENCILS / c->N);
     return (K < 2) ? 1 : K;
 }
 
-hipError_t ahead_alloc(rbfsl_ctx *c, int64_t K) {
-    if (K <= c->ahead_cap) return hipSuccess;
-    ahead_free(c);
-    const int64_t KN = K * c->N;
-    hipError_t e = hipSuccess;
+int64_t ahead_steps(const rbfsl_ctx *c, int64_t nsteps) {
+    const int64_t Km = ahead_max(c);
+    if (Km < 2 || nsteps < 2) return 1;
+    return std::min(Km, std::max<int64_t>(2, (nsteps + AHEAD_CHUNKS - 1) / AHEAD_CHUNKS));
+}
+
+// both sets at the context's largest chunk, once (a run never reallocates)
+hipError_t ahead_alloc(rbfsl_ctx *c) {
+    if (c->ahead_cap > 0) return hipSuccess;
+    const int64_t K = ahead_max(c), KN = K * c->N;
+    hipError_t e = hipStreamCreateWithFlags(&c->wstream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->run_start, hipEventDisableTiming);
 #define ALLOC(ptr, bytes) if (e == hipSuccess) e = hipMalloc(&(ptr), (bytes))
-    ALLOC(c->aex, sizeof(double) * KN);
-    ALLOC(c->aey, sizeof(double) * KN);
-    ALLOC(c->aez, sizeof(double) * KN);
-    ALLOC(c->aw, sizeof(double) * KN * c->n);
-    if (c->mode == 0) {
-        ALLOC(c->as2, sizeof(double) * KN);
-        ALLOC(c->aS, sizeof(int32_t) * KN * c->n);
-    } else {
-        ALLOC(c->acidx, sizeof(int32_t) * KN);
+#define EVENT(ev) if (e == hipSuccess) e = hipEventCreateWithFlags(&(ev), hipEventDisableTiming)
+    for (rbfsl_ctx::AheadSet &A : c->aset) {
+        ALLOC(A.ex, sizeof(double) * KN);
+        ALLOC(A.ey, sizeof(double) * KN);
+        ALLOC(A.ez, sizeof(double) * KN);
+        ALLOC(A.w, sizeof(double) * KN * c->n);
+        if (c->mode == 0) {
+            ALLOC(A.s2, sizeof(double) * KN);
+            ALLOC(A.S, sizeof(int32_t) * KN * c->n);
+        } else {
+            ALLOC(A.cidx, sizeof(int32_t) * KN);
+        }
+        ALLOC(A.sc, sizeof(StepCoef) * K);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&A.sc_host, sizeof(StepCoef) * K, hipHostMallocMapped);
+        if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&A.sc_mapped, A.sc_host, 0);
+        EVENT(A.staged);
+        EVENT(A.solved);
+        EVENT(A.applied);
     }
-    ALLOC(c->asc, sizeof(StepCoef) * K);
+#undef EVENT
 #undef ALLOC
-    for (int b = 0; b < 2 && e == hipSuccess; ++b) {
-        e = hipHostMalloc((void **)&c->asc_host[b], sizeof(StepCoef) * K, hipHostMallocDefault);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->asc_done[b], hipEventDisableTiming);
-    }
     if (e != hipSuccess) {
         ahead_free(c);
         return e;
@@ -435,72 +492,108 @@ hipError_t ahead_alloc(rbfsl_ctx *c, int64_t K) {
     return hipSuccess;
 }
 
-// steps m .. m + K - 1; q^m is in q[par]; chunk parity cb selects the staging
-hipError_t enqueue_steps(rbfsl_ctx *c, int64_t m, int K, int par, int cb) {
-    hipError_t e;
-    if (c->asc_used[cb] && (e = hipEventSynchronize(c->asc_done[cb])) != hipSuccess) return e;
-    for (int s = 0; s < K; ++s) c->asc_host[cb][s] = make_step_coef(c->p, m + s);
-    if ((e = hipMemcpyAsync(c->asc, c->asc_host[cb], sizeof(StepCoef) * K, hipMemcpyHostToDevice, c->stream)) !=
-        hipSuccess)
-        return e;
-    if ((e = hipEventRecord(c->asc_done[cb], c->stream)) != hipSuccess) return e;
-    c->asc_used[cb] = true;
-    const int64_t N = c->N, KN = (int64_t)K * N;
-    if ((e = prof_mark(c, 0)) != hipSuccess) return e;
-    if ((e = launch_trace_steps(c->nx, c->ny, c->nz, N, c->asc, K, c->aex, c->aey, c->aez, c->status, m,
-                                c->stream)) != hipSuccess)
-        return e;
-    if ((e = prof_mark(c, 1)) != hipSuccess) return e;
-    if (c->mode == 0)
-        e = launch_knn(c->grid, N, c->aex, c->aey, c->aez, KN, c->n, c->aS, nullptr, c->as2, c->status, m, c->stream, N);
-    else
-        e = launch_knn(c->grid, N, c->aex, c->aey, c->aez, KN, 1, c->acidx, nullptr, nullptr, c->status, m, c->stream, N);
-    if (e != hipSuccess) return e;
-    if ((e = prof_mark(c, 2)) != hipSuccess) return e;
-    SolveArgs a{};
-    a.nx = c->nx; a.ny = c->ny; a.nz = c->nz; a.N = N;
-    a.ex = c->aex; a.ey = c->aey; a.ez = c->aez;
-    if (c->mode == 1) {
-        a.cx = c->nx; a.cy = c->ny; a.cz = c->nz;
-        a.cidx = c->acidx;
-        a.S = c->S; a.s2 = c->s2;
+// the debug taps show step s of set cb
+void taps_ahead(rbfsl_ctx *c, int cb, int64_t s) {
+    const rbfsl_ctx::AheadSet &A = c->aset[cb];
+    const int64_t N = c->N, n = c->n;
+    c->tex = A.ex + s * N; c->tey = A.ey + s * N; c->tez = A.ez + s * N;
+    c->tw = A.w + s * N * n;
+    if (c->mode == 0) {
+        c->tS = A.S + s * N * n;
+        c->tcidx = nullptr;
     } else {
-        a.S = c->aS; a.s2 = c->as2;
+        c->tS = c->S;
+        c->tcidx = A.cidx + s * N;
     }
-    a.count = KN; a.n = c->n; a.L = c->L; a.k = c->k;
-    a.w = c->aw; a.st_out = nullptr; a.status = c->status; a.step = m; a.step_count = N;
-    if ((e = launch_solve(a, c->stream)) != hipSuccess) return e;
-    if ((e = prof_mark(c, 3)) != hipSuccess) return e;
-    // the K field updates, one launch each (one workgroup holding the field
-    // in LDS across the steps measured 3x slower at N = 1,024: a single
-    // compute unit cannot stream the steps' weights fast enough)
-    const int32_t *Sb = (c->mode == 0) ? c->aS : c->S;
-    const int64_t sstride = (c->mode == 0) ? N * c->n : 0;
-    for (int s = 0; s < K && e == hipSuccess; ++s)
-        e = launch_apply(c->aw + (int64_t)s * N * c->n, Sb + s * sstride,
-                         (c->mode == 1) ? c->acidx + s * N : nullptr, N, c->n, c->ntr, c->q[par ^ (s & 1)],
-                         c->q[par ^ ((s + 1) & 1)], c->status, m + s, c->stream);
-    if (e != hipSuccess) return e;
-    if ((e = prof_mark(c, 4)) != hipSuccess) return e;
-    if (c->prof && !c->ev_steps.empty()) c->ev_steps.back() = K;
-    return hipSuccess;
 }
 
-// the last step's departure points, stencils and weights to the single-step
-// buffers (what the debug taps read)
-hipError_t ahead_publish(rbfsl_ctx *c, int s) {
-    const int64_t N = c->N, n = c->n;
-    const hipMemcpyKind k = hipMemcpyDeviceToDevice;
-    hipError_t e = hipMemcpyAsync(c->ex, c->aex + s * N, sizeof(double) * N, k, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(c->ey, c->aey + s * N, sizeof(double) * N, k, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(c->ez, c->aez + s * N, sizeof(double) * N, k, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(c->w, c->aw + s * N * n, sizeof(double) * N * n, k, c->stream);
-    if (c->mode == 0) {
-        if (e == hipSuccess) e = hipMemcpyAsync(c->S, c->aS + s * N * n, sizeof(int32_t) * N * n, k, c->stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(c->s2, c->as2 + s * N, sizeof(double) * N, k, c->stream);
+// The departure points, stencils and weights of steps m .. m + K - 1 into set
+// cb, on wstream, after the field updates that last read the set.
+hipError_t enqueue_weights(rbfsl_ctx *c, int64_t m, int K, int cb, int64_t g) {
+    rbfsl_ctx::AheadSet &A = c->aset[cb];
+    const hipStream_t ws = c->wstream;
+    hipError_t e;
+    if (A.used && (e = hipEventSynchronize(A.staged)) != hipSuccess) return e;
+    for (int s = 0; s < K; ++s) A.sc_host[s] = make_step_coef(c->p, m + s);
+    if (A.used && (e = hipStreamWaitEvent(ws, A.applied, 0)) != hipSuccess) return e;
+    static_assert(sizeof(StepCoef) % sizeof(uint64_t) == 0, "StepCoef is staged as 64-bit words");
+    const int64_t nwords = (int64_t)(sizeof(StepCoef) / sizeof(uint64_t)) * K;
+    hipLaunchKernelGGL(k_stage_words, dim3((unsigned)((nwords + 255) / 256)), dim3(256), 0, ws,
+                       (const uint64_t *)A.sc_mapped, (uint64_t *)A.sc, nwords);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipEventRecord(A.staged, ws)) != hipSuccess) return e;
+    A.used = true;
+    const int64_t N = c->N, KN = (int64_t)K * N;
+    if ((e = prof_mark(c, g, 0, ws)) != hipSuccess) return e;
+    if ((e = launch_trace_steps(c->nx, c->ny, c->nz, N, A.sc, K, A.ex, A.ey, A.ez, c->status, m, ws)) != hipSuccess)
+        return e;
+    if ((e = prof_mark(c, g, 1, ws)) != hipSuccess) return e;
+    if (c->mode == 0)
+        e = launch_knn(c->grid, N, A.ex, A.ey, A.ez, KN, c->n, A.S, nullptr, A.s2, c->status, m, ws, N);
+    else
+        e = launch_knn(c->grid, N, A.ex, A.ey, A.ez, KN, 1, A.cidx, nullptr, nullptr, c->status, m, ws, N);
+    if (e != hipSuccess) return e;
+    if ((e = prof_mark(c, g, 2, ws)) != hipSuccess) return e;
+    SolveArgs a{};
+    a.nx = c->nx; a.ny = c->ny; a.nz = c->nz; a.N = N;
+    a.ex = A.ex; a.ey = A.ey; a.ez = A.ez;
+    if (c->mode == 1) {
+        a.cx = c->nx; a.cy = c->ny; a.cz = c->nz;
+        a.cidx = A.cidx;
+        a.S = c->S; a.s2 = c->s2;
     } else {
-        if (e == hipSuccess) e = hipMemcpyAsync(c->cidx, c->acidx + s * N, sizeof(int32_t) * N, k, c->stream);
+        a.S = A.S; a.s2 = A.s2;
     }
+    a.count = KN; a.n = c->n; a.L = c->L; a.k = c->k;
+    a.w = A.w; a.st_out = nullptr; a.status = c->status; a.step = m; a.step_count = N;
+    if ((e = launch_solve(a, ws)) != hipSuccess) return e;
+    if ((e = prof_mark(c, g, 3, ws)) != hipSuccess) return e;
+    return hipEventRecord(A.solved, ws);
+}
+
+// The K field updates of steps m .. m + K - 1 from set cb, one launch each, on
+// the context's stream after that set's solve; q^m is in q[par].  (One
+// workgroup holding the field in LDS across the steps measured 3x slower at
+// N = 1,024: a single compute unit cannot stream the steps' weights fast
+// enough.)
+hipError_t enqueue_applies(rbfsl_ctx *c, int64_t m, int K, int par, int cb, int64_t g) {
+    rbfsl_ctx::AheadSet &A = c->aset[cb];
+    const int64_t N = c->N;
+    hipError_t e;
+    if ((e = hipStreamWaitEvent(c->stream, A.solved, 0)) != hipSuccess) return e;
+    if ((e = prof_mark(c, g, 4)) != hipSuccess) return e;
+    const int32_t *Sb = (c->mode == 0) ? A.S : c->S;
+    const int64_t sstride = (c->mode == 0) ? N * c->n : 0;
+    for (int s = 0; s < K && e == hipSuccess; ++s)
+        e = launch_apply(A.w + (int64_t)s * N * c->n, Sb + s * sstride,
+                         (c->mode == 1) ? A.cidx + s * N : nullptr, N, c->n, c->ntr, c->q[par ^ (s & 1)],
+                         c->q[par ^ ((s + 1) & 1)], c->status, m + s, c->stream);
+    if (e != hipSuccess) return e;
+    if ((e = prof_mark(c, g, 5)) != hipSuccess) return e;
+    return hipEventRecord(A.applied, c->stream);
+}
+
+// A run of nsteps steps in chunks of K from step m0 (q^m0 in q[cur0]): each
+// chunk's weights are enqueued before the previous chunk's field updates, so
+// that the host never holds the weights stream back behind a row of updates.
+hipError_t enqueue_chunks(rbfsl_ctx *c, int64_t m0, int64_t nsteps, int64_t K, int cur0, int64_t *mfail) {
+    const int64_t nch = (nsteps + K - 1) / K;
+    std::vector<int64_t> grp((size_t)nch, -1);
+    auto kc = [&](int64_t j) { return (int)std::min<int64_t>(K, nsteps - j * K); };
+    hipError_t e = hipSuccess;
+    for (int64_t j = 0; j <= nch && e == hipSuccess; ++j) {
+        if (j < nch) {
+            *mfail = m0 + j * K;
+            e = prof_group(c, kc(j), &grp[(size_t)j]);
+            if (e == hipSuccess) e = enqueue_weights(c, m0 + j * K, kc(j), (int)(j & 1), grp[(size_t)j]);
+        }
+        if (j > 0 && e == hipSuccess) {
+            const int64_t i = j - 1;
+            *mfail = m0 + i * K;
+            e = enqueue_applies(c, m0 + i * K, kc(i), cur0 ^ (int)((i * K) & 1), (int)(i & 1), grp[(size_t)i]);
+        }
+    }
+    if (e == hipSuccess) taps_ahead(c, (int)((nch - 1) & 1), kc(nch - 1) - 1);
     return e;
 }
 
@@ -651,6 +744,7 @@ int rbfsl_create(const double *nodes_xyz, int64_t N, int nodes_on_device, const 
         delete c;
         return code;
     }
+    taps_single(c);
     *out = c;
     return RBFSL_OK;
 }
@@ -751,6 +845,7 @@ int rbfsl_create_pu(const double *nodes_xyz, int64_t N, int nodes_on_device, con
         delete c;
         return code;
     }
+    taps_single(c);
     *out = c;
     return RBFSL_OK;
 }
@@ -790,21 +885,20 @@ int rbfsl_run(rbfsl_ctx *c, int64_t nsteps) {
     const int cur0 = c->cur;
     const int64_t K = ahead_steps(c, nsteps);
     if (K > 1) {
-        HIP_TRY(c, ahead_alloc(c, K));
-        int cb = 0;
-        int64_t last = 0;
-        for (int64_t m = m0; m < m0 + nsteps; m += K, cb ^= 1) {
-            const int Kc = (int)std::min<int64_t>(K, m0 + nsteps - m);
-            hipError_t e = enqueue_steps(c, m, Kc, cur0 ^ (int)((m - m0) & 1), cb);
-            if (e != hipSuccess) {
-                (void)hipStreamSynchronize(c->stream);
-                c->cur = cur0;
-                return fail(c, RBFSL_E_DEVICE, "steps %lld.. launch: %s", (long long)m, hipGetErrorString(e));
-            }
-            last = Kc - 1;
+        HIP_TRY(c, ahead_alloc(c));
+        // the tracer, search and solve stream starts after the status reset
+        HIP_TRY(c, hipEventRecord(c->run_start, c->stream));
+        HIP_TRY(c, hipStreamWaitEvent(c->wstream, c->run_start, 0));
+        int64_t m = m0;
+        const hipError_t e = enqueue_chunks(c, m0, nsteps, K, cur0, &m);
+        if (e != hipSuccess) {
+            (void)hipStreamSynchronize(c->wstream);
+            (void)hipStreamSynchronize(c->stream);
+            c->cur = cur0;
+            return fail(c, RBFSL_E_DEVICE, "steps %lld.. launch: %s", (long long)m, hipGetErrorString(e));
         }
-        HIP_TRY(c, ahead_publish(c, (int)last));
     } else {
+        taps_single(c);
         for (int64_t m = m0; m < m0 + nsteps; ++m) {
             c->cur = cur0 ^ (int)((m - m0) & 1);  // buffer holding q^m
             hipError_t e = enqueue_step(c, m);
@@ -891,7 +985,7 @@ int rbfsl_phase_times(rbfsl_ctx *c, double *ms, int64_t *steps) {
 int rbfsl_debug_departure(rbfsl_ctx *c, double *xi) {
     if (!c || !xi) return RBFSL_E_INVAL;
     if (!c->ran) return fail(c, RBFSL_E_STATE, "no step has run");
-    HIP_TRY(c, download_points(c->ex, c->ey, c->ez, c->N, xi, c->stream));
+    HIP_TRY(c, download_points(c->tex, c->tey, c->tez, c->N, xi, c->stream));
     return RBFSL_OK;
 }
 
@@ -900,12 +994,12 @@ int rbfsl_debug_stencils(rbfsl_ctx *c, int32_t *idx) {
     if (!c->ran) return fail(c, RBFSL_E_STATE, "no step has run");
     const size_t bytes = sizeof(int32_t) * c->N * c->n;
     if (c->mode == 0) {
-        HIP_TRY(c, hipMemcpyAsync(idx, c->S, bytes, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(idx, c->tS, bytes, hipMemcpyDeviceToHost, c->stream));
     } else {
         int32_t *tmp = nullptr;
         HIP_TRY(c, hipMalloc(&tmp, bytes));
         hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((c->N * c->n + 255) / 256)), dim3(256), 0,
-                           c->stream, c->S, c->cidx, c->N, c->n, tmp);
+                           c->stream, c->tS, c->tcidx, c->N, c->n, tmp);
         hipError_t e = hipGetLastError();
         if (e == hipSuccess) e = hipMemcpyAsync(idx, tmp, bytes, hipMemcpyDeviceToHost, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -919,7 +1013,7 @@ int rbfsl_debug_stencils(rbfsl_ctx *c, int32_t *idx) {
 int rbfsl_debug_weights(rbfsl_ctx *c, double *w) {
     if (!c || !w || c->mode == RBFSL_STENCIL_PU) return RBFSL_E_INVAL;
     if (!c->ran) return fail(c, RBFSL_E_STATE, "no step has run");
-    HIP_TRY(c, hipMemcpyAsync(w, c->w, sizeof(double) * c->N * c->n, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(w, c->tw, sizeof(double) * c->N * c->n, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return RBFSL_OK;
 }
@@ -941,8 +1035,8 @@ int rbfsl_debug_sample(rbfsl_ctx *c, const int64_t *jl, int64_t J, double *xi, i
     if (e == hipSuccess && w) e = hipMalloc(&dw, d * J * nn);
     if (e == hipSuccess) e = hipMemcpyAsync(djl, jl, sizeof(int64_t) * J, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_gather_sample, dim3((unsigned)J), dim3(64), 0, c->stream, djl, J, c->ex, c->ey,
-                           c->ez, c->S, c->mode == 1 ? c->cidx : nullptr, c->w, c->n, dxi, dS, dw);
+        hipLaunchKernelGGL(k_gather_sample, dim3((unsigned)J), dim3(64), 0, c->stream, djl, J, c->tex, c->tey,
+                           c->tez, c->tS, c->mode == 1 ? c->tcidx : nullptr, c->tw, c->n, dxi, dS, dw);
         e = hipGetLastError();
     }
     if (e == hipSuccess && xi) e = hipMemcpyAsync(xi, dxi, d * 3 * J, hipMemcpyDeviceToHost, c->stream);
