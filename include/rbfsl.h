@@ -160,9 +160,10 @@ int rbfsl_step(rbfsl_ctx *ctx);
  * prescribed, eq. sl_ode), so the tracer, search and solve of K consecutive
  * steps each run as one launch over K N points (K = rbfsl_steps_per_launch),
  * then the K field updates follow in step order.  The run is cut into chunks
- * of K steps whose tracer, search and solve run on a second stream of the
- * library's, each chunk's while the field updates of the one before run on
- * hip_stream; its buffers (two chunks of departure points, stencils and
+ * of K steps (a last chunk of more than K/2 steps in two halves when K >= 8)
+ * whose tracer, search and solve run on a second stream of the library's,
+ * each chunk's while the field updates of the one before run on hip_stream;
+ * its buffers (two chunks of departure points, stencils and
  * weights) are allocated by the first such run and kept until
  * rbfsl_destroy.  In that mode the failure
  * counts of rbfsl_get_failures may include stencils of steps after the first
@@ -171,9 +172,9 @@ int rbfsl_step(rbfsl_ctx *ctx);
  * last step. */
 int rbfsl_run(rbfsl_ctx *ctx, int64_t nsteps);
 
-/* Steps per launch that rbfsl_run(ctx, nsteps) takes: 1 for the step-by-step
- * path, else K >= 2: a quarter of nsteps rounded up, at least 2, at most
- * 131,072 / N and 128. */
+/* Steps per launch that rbfsl_run(ctx, nsteps) takes at most: 1 for the
+ * step-by-step path, else K >= 2: a quarter of nsteps rounded up, at least 2,
+ * at most 131,072 / N and 128. */
 int64_t rbfsl_steps_per_launch(const rbfsl_ctx *ctx, int64_t nsteps);
 
 /* Copy q^m, Algorithm 1's state after m steps, out (n_tracers x N).

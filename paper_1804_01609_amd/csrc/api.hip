@@ -576,24 +576,38 @@ hipError_t enqueue_applies(rbfsl_ctx *c, int64_t m, int K, int par, int cb, int6
 // A run of nsteps steps in chunks of K from step m0 (q^m0 in q[cur0]): each
 // chunk's weights are enqueued before the previous chunk's field updates, so
 // that the host never holds the weights stream back behind a row of updates.
+// The last chunk's updates run after every solve has ended; when chunks are
+// long (K >= 8) a last chunk of more than K/2 steps is cut in two halves, so
+// that fewer of them wait.
 hipError_t enqueue_chunks(rbfsl_ctx *c, int64_t m0, int64_t nsteps, int64_t K, int cur0, int64_t *mfail) {
-    const int64_t nch = (nsteps + K - 1) / K;
-    std::vector<int64_t> grp((size_t)nch, -1);
-    auto kc = [&](int64_t j) { return (int)std::min<int64_t>(K, nsteps - j * K); };
+    std::vector<int64_t> size;
+    for (int64_t left = nsteps; left > 0;) {
+        const int64_t k = std::min(K, left);
+        if (k == left && K >= 8 && 2 * k > K) {
+            size.push_back((k + 1) / 2);
+            size.push_back(k / 2);
+        } else {
+            size.push_back(k);
+        }
+        left -= k;
+    }
+    const size_t nch = size.size();
+    std::vector<int64_t> first(nch), grp(nch, -1);
+    for (size_t j = 0, m = 0; j < nch; m += (size_t)size[j], ++j) first[j] = (int64_t)m;
     hipError_t e = hipSuccess;
-    for (int64_t j = 0; j <= nch && e == hipSuccess; ++j) {
+    for (size_t j = 0; j <= nch && e == hipSuccess; ++j) {
         if (j < nch) {
-            *mfail = m0 + j * K;
-            e = prof_group(c, kc(j), &grp[(size_t)j]);
-            if (e == hipSuccess) e = enqueue_weights(c, m0 + j * K, kc(j), (int)(j & 1), grp[(size_t)j]);
+            *mfail = m0 + first[j];
+            e = prof_group(c, size[j], &grp[j]);
+            if (e == hipSuccess) e = enqueue_weights(c, m0 + first[j], (int)size[j], (int)(j & 1), grp[j]);
         }
         if (j > 0 && e == hipSuccess) {
-            const int64_t i = j - 1;
-            *mfail = m0 + i * K;
-            e = enqueue_applies(c, m0 + i * K, kc(i), cur0 ^ (int)((i * K) & 1), (int)(i & 1), grp[(size_t)i]);
+            const size_t i = j - 1;
+            *mfail = m0 + first[i];
+            e = enqueue_applies(c, m0 + first[i], (int)size[i], cur0 ^ (int)(first[i] & 1), (int)(i & 1), grp[i]);
         }
     }
-    if (e == hipSuccess) taps_ahead(c, (int)((nch - 1) & 1), kc(nch - 1) - 1);
+    if (e == hipSuccess) taps_ahead(c, (int)((nch - 1) & 1), size[nch - 1] - 1);
     return e;
 }
 

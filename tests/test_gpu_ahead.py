@@ -45,7 +45,7 @@ CASES = [
     (1024, 31, 3, 2, 0, 1, 40),
     (1024, 31, 3, 2, 1, 1, 40),
     (1024, 31, 3, 2, 0, 8, 24),
-    (5000, 39, 4, 2, 0, 1, 30),    # 8 steps per launch: four chunks, the last partial
+    (5000, 39, 4, 2, 0, 1, 30),    # chunks of 8, 8, 8, 3, 3 steps
     (2562, 56, 4, 2, 1, 2, 60),
 ]
 
@@ -62,7 +62,7 @@ def test_run_equals_single_steps(N, n, L, k, mode, ntr, steps):
 
 
 def test_chunk_boundaries_and_resumed_runs():
-    # runs of 300 = 4 x 75, and 129 = 3 x 33 + 30 then 171 = 3 x 43 + 42 steps
+    # runs of 300 = 3 x 75 + 38 + 37, and 129 = 3 x 33 + 15 + 15 then 171 = 3 x 43 + 21 + 21 steps
     N, n, L, k = 1024, 31, 3, 2
     X = W.fibonacci_nodes(N)
     q0 = W.c1_bump(X)[None]
