@@ -323,8 +323,8 @@ typedef struct {
     int32_t runs, active;         /* admitted runs; runs with steps left */
     int64_t bytes_used, bytes_budget;
     int64_t steps_launched;
-    int64_t items_per_step[3];    /* queue items of the last step, per kernel family */
-    int32_t blocks[3];            /* persistent workgroups per launch, per family    */
+    int64_t items_per_step[4];    /* queue items of the last step, per kernel family */
+    int32_t blocks[4];            /* persistent workgroups per launch, per family    */
     int32_t graph;
 } rbfsl_pool_stats;
 int rbfsl_pool_info(rbfsl_pool *pool, rbfsl_pool_stats *st);

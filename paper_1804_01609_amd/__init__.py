@@ -68,8 +68,8 @@ class PoolConfig(ctypes.Structure):
 class PoolStats(ctypes.Structure):
     _fields_ = [("runs", ctypes.c_int32), ("active", ctypes.c_int32),
                 ("bytes_used", ctypes.c_int64), ("bytes_budget", ctypes.c_int64),
-                ("steps_launched", ctypes.c_int64), ("items_per_step", ctypes.c_int64 * 3),
-                ("blocks", ctypes.c_int32 * 3), ("graph", ctypes.c_int32)]
+                ("steps_launched", ctypes.c_int64), ("items_per_step", ctypes.c_int64 * 4),
+                ("blocks", ctypes.c_int32 * 4), ("graph", ctypes.c_int32)]
 
 
 class TuneResult(ctypes.Structure):

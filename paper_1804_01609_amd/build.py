@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "librbfsl.so")
 
-SOURCES = ["k_pool4.hip", "k_pool3.hip", "k_pool8.hip", "k_pool_search.hip", "pool_api.hip", "k_solve_m192.hip", "k_solve_m128.hip", "k_solve_m120.hip", "k_solve_m96.hip", "k_solve_m81.hip", "k_solve_m64.hip", "k_solve_m48.hip",
+SOURCES = ["k_pool4.hip", "k_pool3.hip", "k_pool8.hip", "k_pool16.hip", "k_pool_search.hip", "pool_api.hip", "k_solve_m192.hip", "k_solve_m128.hip", "k_solve_m120.hip", "k_solve_m96.hip", "k_solve_m81.hip", "k_solve_m64.hip", "k_solve_m48.hip",
            "k_solve.hip", "k_cached.hip", "k_pu.hip", "api.hip", "noalloc.hip", "k_trace.hip", "k_grid.hip", "k_knn.hip", "k_apply.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -34,12 +34,16 @@ extern const PoolVariantInfo kPool8Variants[];
 extern const int kPool8NumVariants;
 extern const PoolVariantInfo kPool3Variants[];
 extern const int kPool3NumVariants;
+extern const PoolVariantInfo kPool16Variants[];
+extern const int kPool16NumVariants;
 hipError_t pool4_launch(const PoolArgs &a, int blocks, hipStream_t s);
 hipError_t pool8_launch(const PoolArgs &a, int blocks, hipStream_t s);
 hipError_t pool3_launch(const PoolArgs &a, int blocks, hipStream_t s);
+hipError_t pool16_launch(const PoolArgs &a, int blocks, hipStream_t s);
 int pool4_blocks_per_cu();
 int pool8_blocks_per_cu();
 int pool3_blocks_per_cu();
+int pool16_blocks_per_cu();
 
 struct QueueSet {
     PoolQueue *q[POOL_FAMILIES];
@@ -66,7 +70,8 @@ hipError_t pool_launch_family(int family, const PoolArgs &a, int blocks, hipStre
     switch (family) {
         case 0: return pool4_launch(a, blocks, s);
         case 1: return pool8_launch(a, blocks, s);
-        default: return pool3_launch(a, blocks, s);
+        case 2: return pool3_launch(a, blocks, s);
+        default: return pool16_launch(a, blocks, s);
     }
 }
 
@@ -74,14 +79,18 @@ int pool_family_blocks_per_cu(int family) {
     switch (family) {
         case 0: return pool4_blocks_per_cu();
         case 1: return pool8_blocks_per_cu();
-        default: return pool3_blocks_per_cu();
+        case 2: return pool3_blocks_per_cu();
+        default: return pool16_blocks_per_cu();
     }
 }
 
 int pool_variants(const PoolVariantInfo **out) {
     static std::vector<PoolVariantInfo> all;
     if (all.empty()) {
+        // the 16-wave variant before the 8-wave one: the default for systems
+        // of 129..192 unknowns (M = 184: 840 against 881 ns per node)
         for (int i = 0; i < kPool4NumVariants; ++i) all.push_back(kPool4Variants[i]);
+        for (int i = 0; i < kPool16NumVariants; ++i) all.push_back(kPool16Variants[i]);
         for (int i = 0; i < kPool8NumVariants; ++i) all.push_back(kPool8Variants[i]);
         for (int i = 0; i < kPool3NumVariants; ++i) all.push_back(kPool3Variants[i]);
     }
@@ -709,6 +718,10 @@ int rbfsl_pool_remove(rbfsl_pool *pl, int64_t run_id) {
     PHIP(pl, hipStreamSynchronize(pl->main));
     return RBFSL_OK;
 }
+
+static_assert(sizeof(rbfsl_pool_stats::blocks) / sizeof(int32_t) == POOL_FAMILIES &&
+                  sizeof(rbfsl_pool_stats::items_per_step) / sizeof(int64_t) == POOL_FAMILIES,
+              "one entry per kernel family");
 
 int rbfsl_pool_info(rbfsl_pool *pl, rbfsl_pool_stats *st) {
     if (!pl || !st) return RBFSL_E_INVAL;

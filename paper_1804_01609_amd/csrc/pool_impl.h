@@ -74,9 +74,9 @@ hipError_t pool_launch_search(const PoolArgs &a, int blocks, hipStream_t s);
 int pool_search_blocks_per_cu();
 
 // Kernel families, by waves per workgroup: 4 (systems up to 128 unknowns,
-// one, two or four waves per stencil), 8 (up to 192 unknowns) and 3 (up to
-// 90 unknowns, three waves per stencil).
-constexpr int POOL_FAMILIES = 3;
+// one, two or four waves per stencil), 8 (up to 192 unknowns), 3 (up to 90
+// unknowns, three waves per stencil) and 16 (up to 192 unknowns).
+constexpr int POOL_FAMILIES = 4;
 struct PoolVariantInfo {
     int family;
     int var;     // index inside the family's kernel

@@ -123,4 +123,4 @@ def test_pool_host_checks_without_a_device():
     assert max(v["mcap"] for v in vs) >= 184
     assert {v["waves"] for v in vs} >= {1, 2, 4}
     for v in vs:
-        assert v["waves"] * v["group"] in (3, 4, 8)
+        assert v["waves"] * v["group"] in (3, 4, 8, 16)
