@@ -55,12 +55,13 @@ __global__ void k_pool_reset(QueueSet qs) {
 
 // advance every slot whose step went through: not finished, no failure at or
 // before the step
-__global__ void k_pool_commit(const PoolRunDev *runs, PoolState *state, int nslots) {
+// on[s]: slot s took part in the step (its nodes were in the queues)
+__global__ void k_pool_commit(const PoolRunDev *runs, PoolState *state, const int *on, int nslots) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= nslots) return;
     const PoolRunDev &r = runs[s];
     PoolState &st = state[s];
-    if (r.nsteps > 0 && st.step < r.nsteps && r.status[ST_FAILSTEP] > st.step) {
+    if (on[s] && r.nsteps > 0 && st.step < r.nsteps && r.status[ST_FAILSTEP] > st.step) {
         st.step += 1;
         st.cur ^= 1;
     }
@@ -192,7 +193,9 @@ struct Run {
     char *block = nullptr;
     size_t bytes = 0;
     RunLayout lay{};
+    bool hold = false;  // left out of the next steps (the served form's scheduler)
     bool in_table() const { return used && !failed && h_step < nsteps; }
+    bool stepping() const { return in_table() && !hold; }
 };
 
 }  // namespace
@@ -213,6 +216,7 @@ struct rbfsl_pool {
     std::map<int64_t, int> slot_of;  // run id -> slot
     PoolRunDev *d_runs = nullptr, *h_runs = nullptr;   // h_*: pinned mirrors
     PoolState *d_state = nullptr, *h_state = nullptr;
+    int *d_on = nullptr, *h_on[2] = {};                // slots taking part in the step (ring as the queues)
     int *d_status = nullptr, *h_status = nullptr;      // max_runs x ST_WORDS
     // queues: one per kernel family, and the search pass's (index SEARCH)
     PoolQueue *d_queue[POOL_FAMILIES + 1] = {};
@@ -288,7 +292,7 @@ int upload_tables(rbfsl_pool *pl) {
     pl->qring ^= 1;
     std::vector<int> order;
     for (int s = 0; s < pl->max_runs; ++s)
-        if (pl->runs[s].in_table()) order.push_back(s);
+        if (pl->runs[s].stepping()) order.push_back(s);
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return pl->runs[a].M > pl->runs[b].M; });
     for (int f = 0; f <= POOL_FAMILIES; ++f) {
@@ -318,6 +322,11 @@ int upload_tables(rbfsl_pool *pl) {
         if (!search) pl->items_last[f] = item;
         const size_t bytes = offsetof(PoolQueue, seg) + sizeof(PoolSeg) * (size_t)ns;
         PHIP(pl, hipMemcpyAsync(pl->d_queue[f], h, bytes, hipMemcpyHostToDevice, pl->main));
+        if (search) {  // the commit's list, behind the same staging event
+            int *on = pl->h_on[ring];
+            for (int s = 0; s < pl->max_runs; ++s) on[s] = pl->runs[s].stepping() ? 1 : 0;
+            PHIP(pl, hipMemcpyAsync(pl->d_on, on, sizeof(int) * pl->max_runs, hipMemcpyHostToDevice, pl->main));
+        }
         PHIP(pl, hipEventRecord(pl->qev[f][ring], pl->main));
     }
     pl->dirty = false;
@@ -352,7 +361,8 @@ hipError_t enqueue_step_kernels(rbfsl_pool *pl, bool commit) {
     }
     if (commit) {
         const int nb = (pl->max_runs + 255) / 256;
-        hipLaunchKernelGGL(k_pool_commit, dim3(nb), dim3(256), 0, pl->main, pl->d_runs, pl->d_state, pl->max_runs);
+        hipLaunchKernelGGL(k_pool_commit, dim3(nb), dim3(256), 0, pl->main, pl->d_runs, pl->d_state, pl->d_on,
+                           pl->max_runs);
         e = hipGetLastError();
     }
     return e;
@@ -386,7 +396,7 @@ int launch_one_step(rbfsl_pool *pl) {
     }
     pl->steps_launched += 1;
     for (Run &r : pl->runs)
-        if (r.in_table()) {
+        if (r.stepping()) {
             r.h_step += 1;
             if (r.h_step == r.nsteps) pl->dirty = true;
         }
@@ -429,10 +439,10 @@ void pool_free(rbfsl_pool *pl) {
             if (pl->qev[f][r]) (void)hipEventDestroy(pl->qev[f][r]);
         }
     }
-    void *dev[] = {pl->d_runs, pl->d_state, pl->d_status, pl->arena.base};
+    void *dev[] = {pl->d_runs, pl->d_state, pl->d_status, pl->d_on, pl->arena.base};
     for (void *p : dev)
         if (p) (void)hipFree(p);
-    void *host[] = {pl->h_runs, pl->h_state, pl->h_status};
+    void *host[] = {pl->h_runs, pl->h_state, pl->h_status, pl->h_on[0], pl->h_on[1]};
     for (void *p : host)
         if (p) (void)hipHostFree(p);
     hipEvent_t evs[] = {pl->admitted, pl->fork};
@@ -483,6 +493,7 @@ int pool_add_impl(rbfsl_pool *pl, const double *nodes_xyz, int64_t N, int nodes_
     Run &r = pl->runs[s];
     r = Run();
     r.used = true;
+    r.hold = false;
     r.id = pl->next_id++;
     r.N = N;
     r.nsteps = nsteps;
@@ -623,6 +634,8 @@ int rbfsl_pool_create(const rbfsl_pool_config *cfg, rbfsl_pool **out) {
     if (e == hipSuccess) e = hipMalloc(&pl->d_status, sizeof(int) * ST_WORDS * pl->max_runs);
     if (e == hipSuccess) e = hipHostMalloc(&pl->h_runs, sizeof(PoolRunDev) * pl->max_runs, 0);
     if (e == hipSuccess) e = hipHostMalloc(&pl->h_state, sizeof(PoolState) * pl->max_runs, 0);
+    if (e == hipSuccess) e = hipMalloc(&pl->d_on, sizeof(int) * pl->max_runs);
+    for (int r = 0; r < 2 && e == hipSuccess; ++r) e = hipHostMalloc(&pl->h_on[r], sizeof(int) * pl->max_runs, 0);
     if (e == hipSuccess) e = hipHostMalloc(&pl->h_status, sizeof(int) * ST_WORDS * pl->max_runs, 0);
     for (int f = 0; f <= POOL_FAMILIES && e == hipSuccess; ++f) {
         e = hipMalloc(&pl->d_queue[f], sizeof(PoolQueue));
@@ -640,6 +653,7 @@ int rbfsl_pool_create(const rbfsl_pool_config *cfg, rbfsl_pool **out) {
         e = hipMemcpy(pl->d_runs, pl->h_runs, sizeof(PoolRunDev) * pl->max_runs, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(pl->d_state, pl->h_state, sizeof(PoolState) * pl->max_runs, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemset(pl->d_status, 0, sizeof(int) * ST_WORDS * pl->max_runs);
+        if (e == hipSuccess) e = hipMemset(pl->d_on, 0, sizeof(int) * pl->max_runs);
         for (int f = 0; f <= POOL_FAMILIES && e == hipSuccess; ++f) e = hipMemset(pl->d_queue[f], 0, sizeof(PoolQueue));
     }
     for (int f = 0; f < POOL_FAMILIES && e == hipSuccess; ++f) {
@@ -864,6 +878,23 @@ int rbfsl_pool_serve(rbfsl_pool *pl, const rbfsl_request *req, int64_t nreq, rbf
     for (auto &e : ev) PHIP(pl, hipEventCreateWithFlags(&e, hipEventDisableTiming));
     int64_t s = 0;
     int rc = RBFSL_OK;
+    // Each admitted run gets an equal share of the device, not an equal number
+    // of steps: a run's pass grows by its estimated step time whenever it
+    // steps, and a step takes the runs whose pass is within SERVE_QUANTUM_US
+    // of the smallest.  Runs of similar cost step together; a run whose steps
+    // cost k quanta steps about once per k steps of the others, so a small
+    // request is not held to the pace of the largest one admitted.
+    constexpr double SERVE_QUANTUM_US = 20000.0;
+    std::vector<double> pass((size_t)pl->max_runs, 0.0);
+    auto step_cost_us = [](const Run &r) {  // per-node cost ~ 0.03 us x (M / 47)^2.5, plus launch overhead
+        return 50.0 + 0.03 * (double)r.N * pow((double)r.M / 47.0, 2.5);
+    };
+    auto min_pass = [&]() {
+        double v = -1.0;
+        for (int q = 0; q < pl->max_runs; ++q)
+            if (pl->runs[q].in_table() && (v < 0.0 || pass[(size_t)q] < v)) v = pass[(size_t)q];
+        return v < 0.0 ? 0.0 : v;
+    };
     auto finish = [&](int slot, double tnow) -> int {
         Run &r = pl->runs[slot];
         const int64_t i = req_of[r.id];
@@ -900,6 +931,7 @@ int rbfsl_pool_serve(rbfsl_pool *pl, const rbfsl_request *req, int64_t nreq, rbf
                 continue;
             }
             req_of[id] = i;
+            pass[(size_t)pl->slot_of[id]] = min_pass();
         }
         if (active_runs(pl) == 0) {
             if (head == pending.size() && next < order.size()) {
@@ -916,6 +948,17 @@ int rbfsl_pool_serve(rbfsl_pool *pl, const rbfsl_request *req, int64_t nreq, rbf
             }
             if (req_of.empty()) continue;
         } else {
+            const double v = min_pass();
+            for (int q = 0; q < pl->max_runs; ++q) {
+                Run &r = pl->runs[q];
+                if (!r.in_table()) continue;
+                const bool h = pass[(size_t)q] > v + SERVE_QUANTUM_US;
+                if (h != r.hold) {
+                    r.hold = h;
+                    pl->dirty = true;
+                }
+                if (!h) pass[(size_t)q] += step_cost_us(r);
+            }
             rc = launch_one_step(pl);
             if (rc != RBFSL_OK) break;
             hipError_t e = hipEventRecord(ev[s % 3], pl->main);
@@ -939,6 +982,11 @@ int rbfsl_pool_serve(rbfsl_pool *pl, const rbfsl_request *req, int64_t nreq, rbf
         }
     }
     for (auto &e : ev) (void)hipEventDestroy(e);
+    for (Run &r : pl->runs)
+        if (r.hold) {
+            r.hold = false;
+            pl->dirty = true;
+        }
     if (wall_seconds) *wall_seconds = now_s() - t0;
     if (rc == RBFSL_OK) rc = reconcile(pl);
     return rc;
