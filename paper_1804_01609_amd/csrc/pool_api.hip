@@ -55,6 +55,23 @@ __global__ void k_pool_reset(QueueSet qs) {
 
 // advance every slot whose step went through: not finished, no failure at or
 // before the step
+// The step tables (every queue's used part and the commit's slot list) from
+// pinned staging to the device in one launch on the main stream: per-table
+// copy-engine transfers cost tens of microseconds of hand-over each, at every
+// step whose set of stepping runs changed.
+constexpr int STAGE_TABLES = POOL_FAMILIES + 2;
+struct StageList {
+    const uint64_t *src[STAGE_TABLES];
+    uint64_t *dst[STAGE_TABLES];
+    int64_t nwords[STAGE_TABLES];
+};
+__global__ void k_stage_tables(StageList L) {
+    const int e = blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L.nwords[e];
+         i += (int64_t)gridDim.x * blockDim.x)
+        L.dst[e][i] = L.src[e][i];
+}
+
 // on[s]: slot s took part in the step (its nodes were in the queues)
 __global__ void k_pool_commit(const PoolRunDev *runs, PoolState *state, const int *on, int nslots) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -220,8 +237,10 @@ struct rbfsl_pool {
     int *d_status = nullptr, *h_status = nullptr;      // max_runs x ST_WORDS
     // queues: one per kernel family, and the search pass's (index SEARCH)
     PoolQueue *d_queue[POOL_FAMILIES + 1] = {};
-    PoolQueue *h_queue[POOL_FAMILIES + 1][2] = {};
-    hipEvent_t qev[POOL_FAMILIES + 1][2] = {};
+    PoolQueue *h_queue[POOL_FAMILIES + 1][2] = {};     // pinned staging, and its device address
+    const PoolQueue *m_queue[POOL_FAMILIES + 1][2] = {};
+    const int *m_on[2] = {};
+    hipEvent_t tev[2] = {};                            // the staging of ring slot r has been read
     int search_blocks = 0;
     int qring = 0;
     bool dirty = true;
@@ -285,8 +304,9 @@ void set_variant(Run &r, int gi) {
     r.G = v[gi].G;
 }
 
-// the queues of the runs still stepping (costliest systems first), to the
-// device on the main stream through a ring of pinned staging copies
+// the queues of the runs stepping (costliest systems first) and the commit's
+// slot list, to the device on the main stream through a ring of two pinned
+// staging areas
 int upload_tables(rbfsl_pool *pl) {
     const int ring = pl->qring;
     pl->qring ^= 1;
@@ -295,9 +315,10 @@ int upload_tables(rbfsl_pool *pl) {
         if (pl->runs[s].stepping()) order.push_back(s);
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return pl->runs[a].M > pl->runs[b].M; });
+    PHIP(pl, hipEventSynchronize(pl->tev[ring]));  // the staging area is free again
+    StageList L{};
     for (int f = 0; f <= POOL_FAMILIES; ++f) {
         const bool search = (f == POOL_FAMILIES);  // every run, one item per node
-        PHIP(pl, hipEventSynchronize(pl->qev[f][ring]));  // staging copy free again
         PoolQueue *h = pl->h_queue[f][ring];
         int64_t item = 0;
         int ns = 0;
@@ -320,15 +341,19 @@ int upload_tables(rbfsl_pool *pl) {
         h->pad = 0;
         h->next = 0;
         if (!search) pl->items_last[f] = item;
-        const size_t bytes = offsetof(PoolQueue, seg) + sizeof(PoolSeg) * (size_t)ns;
-        PHIP(pl, hipMemcpyAsync(pl->d_queue[f], h, bytes, hipMemcpyHostToDevice, pl->main));
-        if (search) {  // the commit's list, behind the same staging event
-            int *on = pl->h_on[ring];
-            for (int s = 0; s < pl->max_runs; ++s) on[s] = pl->runs[s].stepping() ? 1 : 0;
-            PHIP(pl, hipMemcpyAsync(pl->d_on, on, sizeof(int) * pl->max_runs, hipMemcpyHostToDevice, pl->main));
-        }
-        PHIP(pl, hipEventRecord(pl->qev[f][ring], pl->main));
+        static_assert(offsetof(PoolQueue, seg) % 8 == 0 && sizeof(PoolSeg) % 8 == 0, "staged as 64-bit words");
+        L.src[f] = reinterpret_cast<const uint64_t *>(pl->m_queue[f][ring]);
+        L.dst[f] = reinterpret_cast<uint64_t *>(pl->d_queue[f]);
+        L.nwords[f] = (int64_t)((offsetof(PoolQueue, seg) + sizeof(PoolSeg) * (size_t)ns) / 8);
     }
+    int *on = pl->h_on[ring];
+    for (int s = 0; s < pl->max_runs; ++s) on[s] = pl->runs[s].stepping() ? 1 : 0;
+    L.src[POOL_FAMILIES + 1] = reinterpret_cast<const uint64_t *>(pl->m_on[ring]);
+    L.dst[POOL_FAMILIES + 1] = reinterpret_cast<uint64_t *>(pl->d_on);
+    L.nwords[POOL_FAMILIES + 1] = (pl->max_runs + 1) / 2;  // the lists hold an even count of ints
+    hipLaunchKernelGGL(k_stage_tables, dim3(8, STAGE_TABLES), dim3(256), 0, pl->main, L);
+    PHIP(pl, hipGetLastError());
+    PHIP(pl, hipEventRecord(pl->tev[ring], pl->main));
     pl->dirty = false;
     return RBFSL_OK;
 }
@@ -434,10 +459,8 @@ void pool_free(rbfsl_pool *pl) {
     if (pl->graph) (void)hipGraphDestroy(pl->graph);
     for (int f = 0; f <= POOL_FAMILIES; ++f) {
         if (pl->d_queue[f]) (void)hipFree(pl->d_queue[f]);
-        for (int r = 0; r < 2; ++r) {
+        for (int r = 0; r < 2; ++r)
             if (pl->h_queue[f][r]) (void)hipHostFree(pl->h_queue[f][r]);
-            if (pl->qev[f][r]) (void)hipEventDestroy(pl->qev[f][r]);
-        }
     }
     void *dev[] = {pl->d_runs, pl->d_state, pl->d_status, pl->d_on, pl->arena.base};
     for (void *p : dev)
@@ -445,7 +468,7 @@ void pool_free(rbfsl_pool *pl) {
     void *host[] = {pl->h_runs, pl->h_state, pl->h_status, pl->h_on[0], pl->h_on[1]};
     for (void *p : host)
         if (p) (void)hipHostFree(p);
-    hipEvent_t evs[] = {pl->admitted, pl->fork};
+    hipEvent_t evs[] = {pl->admitted, pl->fork, pl->tev[0], pl->tev[1]};
     for (hipEvent_t e : evs)
         if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : pl->join)
@@ -634,14 +657,20 @@ int rbfsl_pool_create(const rbfsl_pool_config *cfg, rbfsl_pool **out) {
     if (e == hipSuccess) e = hipMalloc(&pl->d_status, sizeof(int) * ST_WORDS * pl->max_runs);
     if (e == hipSuccess) e = hipHostMalloc(&pl->h_runs, sizeof(PoolRunDev) * pl->max_runs, 0);
     if (e == hipSuccess) e = hipHostMalloc(&pl->h_state, sizeof(PoolState) * pl->max_runs, 0);
-    if (e == hipSuccess) e = hipMalloc(&pl->d_on, sizeof(int) * pl->max_runs);
-    for (int r = 0; r < 2 && e == hipSuccess; ++r) e = hipHostMalloc(&pl->h_on[r], sizeof(int) * pl->max_runs, 0);
+    const size_t on_bytes = sizeof(int) * (size_t)((pl->max_runs + 1) & ~1);
+    if (e == hipSuccess) e = hipMalloc(&pl->d_on, on_bytes);
+    for (int r = 0; r < 2 && e == hipSuccess; ++r) {
+        e = hipHostMalloc(&pl->h_on[r], on_bytes, hipHostMallocMapped);
+        if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&pl->m_on[r], pl->h_on[r], 0);
+        if (e == hipSuccess) memset(pl->h_on[r], 0, on_bytes);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->tev[r], hipEventDisableTiming);
+    }
     if (e == hipSuccess) e = hipHostMalloc(&pl->h_status, sizeof(int) * ST_WORDS * pl->max_runs, 0);
     for (int f = 0; f <= POOL_FAMILIES && e == hipSuccess; ++f) {
         e = hipMalloc(&pl->d_queue[f], sizeof(PoolQueue));
         for (int r = 0; r < 2 && e == hipSuccess; ++r) {
-            e = hipHostMalloc(&pl->h_queue[f][r], sizeof(PoolQueue), 0);
-            if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->qev[f][r], hipEventDisableTiming);
+            e = hipHostMalloc(&pl->h_queue[f][r], sizeof(PoolQueue), hipHostMallocMapped);
+            if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&pl->m_queue[f][r], pl->h_queue[f][r], 0);
         }
     }
     if (e == hipSuccess) e = hipMalloc(&pl->arena.base, budget);
@@ -653,7 +682,7 @@ int rbfsl_pool_create(const rbfsl_pool_config *cfg, rbfsl_pool **out) {
         e = hipMemcpy(pl->d_runs, pl->h_runs, sizeof(PoolRunDev) * pl->max_runs, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(pl->d_state, pl->h_state, sizeof(PoolState) * pl->max_runs, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemset(pl->d_status, 0, sizeof(int) * ST_WORDS * pl->max_runs);
-        if (e == hipSuccess) e = hipMemset(pl->d_on, 0, sizeof(int) * pl->max_runs);
+        if (e == hipSuccess) e = hipMemset(pl->d_on, 0, on_bytes);
         for (int f = 0; f <= POOL_FAMILIES && e == hipSuccess; ++f) e = hipMemset(pl->d_queue[f], 0, sizeof(PoolQueue));
     }
     for (int f = 0; f < POOL_FAMILIES && e == hipSuccess; ++f) {
@@ -878,22 +907,16 @@ int rbfsl_pool_serve(rbfsl_pool *pl, const rbfsl_request *req, int64_t nreq, rbf
     for (auto &e : ev) PHIP(pl, hipEventCreateWithFlags(&e, hipEventDisableTiming));
     int64_t s = 0;
     int rc = RBFSL_OK;
-    // Each admitted run gets an equal share of the device, not an equal number
-    // of steps: a run's pass grows by its estimated step time whenever it
-    // steps, and a step takes the runs whose pass is within SERVE_QUANTUM_US
-    // of the smallest.  Runs of similar cost step together; a run whose steps
-    // cost k quanta steps about once per k steps of the others, so a small
-    // request is not held to the pace of the largest one admitted.
-    constexpr double SERVE_QUANTUM_US = 20000.0;
-    std::vector<double> pass((size_t)pl->max_runs, 0.0);
-    auto step_cost_us = [](const Run &r) {  // per-node cost ~ 0.03 us x (M / 47)^2.5, plus launch overhead
-        return 50.0 + 0.03 * (double)r.N * pow((double)r.M / 47.0, 2.5);
-    };
-    auto min_pass = [&]() {
-        double v = -1.0;
-        for (int q = 0; q < pl->max_runs; ++q)
-            if (pl->runs[q].in_table() && (v < 0.0 || pass[(size_t)q] < v)) v = pass[(size_t)q];
-        return v < 0.0 ? 0.0 : v;
+    // Shortest remaining work first, in batches: a step takes the admitted
+    // runs whose estimated remaining device time, divided by 1 + (time since
+    // admission) / SERVE_AGING_S, is at most SERVE_BATCH times the smallest.
+    // Runs of similar remaining work step together; a small request is not
+    // held to the pace of the largest one admitted, and the division lets a
+    // long-admitted run's turn come even while short requests keep arriving.
+    constexpr double SERVE_BATCH = 2.0, SERVE_AGING_S = 30.0;
+    std::vector<double> admitted_at((size_t)pl->max_runs, 0.0);
+    auto step_cost_us = [](const Run &r) {  // per-node cost ~ 0.03 us x (M / 47)^2.5, plus a step's floor
+        return 300.0 + 0.03 * (double)r.N * pow((double)r.M / 47.0, 2.5);
     };
     auto finish = [&](int slot, double tnow) -> int {
         Run &r = pl->runs[slot];
@@ -931,7 +954,7 @@ int rbfsl_pool_serve(rbfsl_pool *pl, const rbfsl_request *req, int64_t nreq, rbf
                 continue;
             }
             req_of[id] = i;
-            pass[(size_t)pl->slot_of[id]] = min_pass();
+            admitted_at[(size_t)pl->slot_of[id]] = res[i].admitted;
         }
         if (active_runs(pl) == 0) {
             if (head == pending.size() && next < order.size()) {
@@ -948,16 +971,24 @@ int rbfsl_pool_serve(rbfsl_pool *pl, const rbfsl_request *req, int64_t nreq, rbf
             }
             if (req_of.empty()) continue;
         } else {
-            const double v = min_pass();
+            const double tq = now_s() - t0;
+            std::vector<double> rem((size_t)pl->max_runs, -1.0);
+            double least = -1.0;
+            for (int q = 0; q < pl->max_runs; ++q) {
+                const Run &r = pl->runs[q];
+                if (!r.in_table()) continue;
+                const double age = tq - admitted_at[(size_t)q];
+                rem[(size_t)q] = (double)(r.nsteps - r.h_step) * step_cost_us(r) / (1.0 + age / SERVE_AGING_S);
+                if (least < 0.0 || rem[(size_t)q] < least) least = rem[(size_t)q];
+            }
             for (int q = 0; q < pl->max_runs; ++q) {
                 Run &r = pl->runs[q];
                 if (!r.in_table()) continue;
-                const bool h = pass[(size_t)q] > v + SERVE_QUANTUM_US;
+                const bool h = rem[(size_t)q] > SERVE_BATCH * least;
                 if (h != r.hold) {
                     r.hold = h;
                     pl->dirty = true;
                 }
-                if (!h) pass[(size_t)q] += step_cost_us(r);
             }
             rc = launch_one_step(pl);
             if (rc != RBFSL_OK) break;
