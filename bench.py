@@ -198,7 +198,7 @@ def main():
     ap.add_argument("--config", default="c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--sections", default="plain,c2,c1,centre,pu,batched,served")
+    ap.add_argument("--sections", default="plain,c2,c1,centre,pu,batched,batched_small,served")
     ap.add_argument("--batched-steps", type=int, default=24)
     ap.add_argument("--served-requests", type=int, default=10)
     ap.add_argument("--served-step-scale", type=float, default=0.25,
@@ -276,6 +276,10 @@ def main():
         out["batched"] = bench_batched(args.batched_steps, sync)
         say(f"batched: {out['batched']['value']:.4g} interpolations/s "
             f"({out['batched']['speedup_vs_plain']:.3f}x the plain path)")
+    if "batched_small" in sections:
+        out["batched_small"] = bench_batched(args.batched_steps, sync, BATCHED_SMALL)
+        say(f"batched, small runs: {out['batched_small']['value']:.4g} interpolations/s "
+            f"({out['batched_small']['speedup_vs_plain']:.3f}x the plain path)")
     if "served" in sections:
         out["served"] = bench_served(args.served_requests, args.served_load, args.served_step_scale)
         sv = out["served"]
@@ -371,10 +375,18 @@ def _run_inputs(r):
     return X, p
 
 
-def bench_batched(steps, sync):
-    """The 64-run batched workload: pool (tuned, graph-replayed) vs the same
-    runs one after another on the plain path, `steps` steps each."""
-    runs = W.batched_runs()
+BATCHED_C4 = ("c4-batched-64runs-N2048..65536-(31,3,2)/(56,4,2)/(84,5,3)-seed0", dict())
+BATCHED_SMALL = ("batched-small-512runs-N256..2048-(31,3,2)/(56,4,2)/(84,5,3)-seed2",
+                 dict(count=512, seed=2, nmin=256, nmax=2048))
+
+
+def bench_batched(steps, sync, which=BATCHED_C4):
+    """A batched workload: pool (tuned, graph-replayed) vs the same runs one
+    after another on the plain path, `steps` steps each.  C4 (64 runs of
+    2,048..65,536 nodes) is the configured one; the small-run mix (512 runs of
+    256..2,048 nodes) is where launches, not arithmetic, bound the plain path."""
+    name, kw = which
+    runs = W.batched_runs(**kw)
     inputs = [(*_run_inputs(r), None) for r in runs]
     inputs = [(X, p, W.run_q0(r, X)) for r, (X, p, _) in zip(runs, inputs)]
     nodes = sum(r["N"] for r in runs)
@@ -402,7 +414,7 @@ def bench_batched(steps, sync):
     for tr in trs:
         tr.close()
     pool_v, plain_v = nodes * steps / dt_pool, nodes * steps / dt_plain
-    return {"workload": "c4-batched-64runs-N2048..65536-(31,3,2)/(56,4,2)/(84,5,3)-seed0",
+    return {"workload": name,
             "runs": len(runs), "nodes_per_step": nodes, "steps": steps,
             "value": pool_v, "unit": "interpolations/s", "ms_per_step": 1e3 * dt_pool / steps,
             "plain_value": plain_v, "plain_ms_per_step": 1e3 * dt_plain / steps,
