@@ -351,11 +351,16 @@ int rbfsl_pool_tune(rbfsl_pool *pool, int32_t trials, rbfsl_tune_result *res, in
 /* Served form: run a stream of requests through the pool with continuous
  * batching.  Request i arrives `arrival` seconds after the call starts; it is
  * admitted first come first served as soon as a slot and HBM are free (while
- * other runs are stepping), steps alongside everything else on the device,
- * and its final q (n_tracers x N, host) is written to q_out.  Host arrays are
- * read during the call only.  res[i]: admission and completion times (seconds
- * after the start), RBFSL_OK or the failure code, steps done.  A request that
- * cannot fit an empty pool gets RBFSL_E_BUDGET. */
+ * other runs are stepping), steps alongside the other admitted runs on the
+ * device, and its final q (n_tracers x N, host) is written to q_out.  Each
+ * pool step takes the admitted runs with the least remaining work: those
+ * whose estimated remaining device time, divided by 1 + (seconds since
+ * admission) / 30, is within twice the smallest; the others wait for that
+ * step (their state is untouched).  The schedule changes when runs step, not
+ * what a run computes: every result is the one the request gets alone.  Host
+ * arrays are read during the call only.  res[i]: admission and completion
+ * times (seconds after the start), RBFSL_OK or the failure code, steps done.
+ * A request that cannot fit an empty pool gets RBFSL_E_BUDGET. */
 typedef struct {
     double arrival;
     const double *nodes_xyz;  /* N x 3, host */
