@@ -273,6 +273,7 @@ int resolve_nlk(int64_t N, int n, int L, int k, int *Lo, int *ko, char *msg, siz
 }
 
 void ahead_free(rbfsl_ctx *c) {
+    if (c->wstream) (void)hipStreamSynchronize(c->wstream);  // nothing of it still reads the sets
     for (rbfsl_ctx::AheadSet &A : c->aset) {
         void *bufs[] = {A.ex, A.ey, A.ez, A.s2, A.w, A.S, A.cidx, A.sc};
         for (void *b : bufs)
