@@ -207,3 +207,28 @@ def test_served_results_equal_alone_and_in_the_mix():
         assert st == oracle.ORC_OK
         assert np.abs(q - qo).max() <= 1e-9
         assert np.array_equal(q, qo)
+
+
+def test_served_small_request_passes_a_large_one():
+    # both arrive at once; the small one has far less remaining work, so the
+    # scheduler steps it alone and it completes first, while the large one's
+    # state waits untouched: both results are still the ones they get alone
+    specs = [(60000, 84, 5, 3, 40), (2000, 31, 3, 2, 40)]
+    items = []
+    for N, n, L, k, ns in specs:
+        X = W.fibonacci_nodes(N)
+        p = rb.make_params(n, L, k, 0, W.VEL_DEFORM, W.deform_vp(5.0), 5.0 / 80, 0.0, 1)
+        items.append(dict(arrival=0.0, nodes=X, params=p, q0=W.two_gaussians(X)[None], nsteps=ns))
+    say("[serve] large and small at t = 0")
+    with rb.Pool(max_runs=4, hbm_budget=4 << 30) as pl:
+        res, outs, _ = pl.serve(items)
+    big, small = res
+    say(f"  finished: large {big['finished']:.3f} s, small {small['finished']:.3f} s")
+    assert big["status"] == small["status"] == rb.RBFSL_OK
+    assert big["steps"] == small["steps"] == 40
+    assert small["finished"] < big["finished"]
+    for it, q in zip(items, outs):
+        with rb.Transport(it["nodes"], it["params"]) as tr:
+            tr.set_q(it["q0"])
+            tr.run(it["nsteps"])
+            assert np.array_equal(q, tr.get_q())
