@@ -154,18 +154,19 @@ int rbfsl_step(rbfsl_ctx *ctx);
  * host synchronisation between them; one synchronisation at the end.  If step
  * f fails, later steps do nothing and the state is left at step f (q^f), with
  * the failure code returned.  The results are those of nsteps rbfsl_step
- * calls, bit for bit.  Small problems (stencil modes 0 and 1 without cached
- * factors, N <= 65,536) take several steps per launch: a step's departure
- * points, stencils and weights do not depend on q (the velocity is
- * prescribed, eq. sl_ode), so the tracer, search and solve of K consecutive
- * steps each run as one launch over K N points (K = rbfsl_steps_per_launch),
- * then the K field updates follow in step order.  The run is cut into chunks
- * of K steps (a last chunk of more than K/2 steps in two halves when K >= 8)
- * whose tracer, search and solve run on a second stream of the library's,
- * each chunk's while the field updates of the one before run on hip_stream;
- * its buffers (two chunks of departure points, stencils and
- * weights) are allocated by the first such run and kept until
- * rbfsl_destroy.  In that mode the failure
+ * calls, bit for bit.  In stencil modes 0 and 1 without cached factors and
+ * for N <= 65,536, a run of two or more steps goes in chunks: a step's departure points,
+ * stencils and weights do not depend on q (the velocity is prescribed, eq.
+ * sl_ode), so the tracer, search and solve of the K steps of a chunk each run
+ * as one launch over K N points (K = rbfsl_steps_per_launch), then the
+ * chunk's K field updates follow in step order.  Chunks
+ * hold K steps (a last chunk of more than K/2 steps in two halves when
+ * K >= 8); a chunk's tracer and search run on one stream of the library's
+ * and its solve on another, overlapping the solve of the chunk before and
+ * the field updates (on hip_stream) of the one before that.  The buffers of
+ * two chunks (departure points, stencils, weights) are allocated by the
+ * first such run and kept until rbfsl_destroy; when they do not fit, runs go
+ * step by step.  In that mode the failure
  * counts of rbfsl_get_failures may include stencils of steps after the first
  * failing one (their launch had already started); the failing step, the
  * state and q are as above.  After the run, the debug taps show the run's
@@ -173,8 +174,8 @@ int rbfsl_step(rbfsl_ctx *ctx);
 int rbfsl_run(rbfsl_ctx *ctx, int64_t nsteps);
 
 /* Steps per launch that rbfsl_run(ctx, nsteps) takes at most: 1 for the
- * step-by-step path, else K >= 2: a quarter of nsteps rounded up, at least 2,
- * at most 131,072 / N and 128. */
+ * step-by-step path (N > 65,536 among others), else K >= 2: a quarter of
+ * nsteps rounded up, at least 2, at most 131,072 / N and 128. */
 int64_t rbfsl_steps_per_launch(const rbfsl_ctx *ctx, int64_t nsteps);
 
 /* Copy q^m, Algorithm 1's state after m steps, out (n_tracers x N).

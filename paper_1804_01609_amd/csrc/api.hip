@@ -43,25 +43,27 @@ struct rbfsl_ctx {
     Grid cgrid;
     double *q[2] = {nullptr, nullptr};
     int cur = 0;
-    // several steps per launch (runs of small problems): two sets, by chunk
-    // parity, of the departure points, stencils and weights of up to
-    // ahead_cap steps with their tracer coefficients (device, and pinned
-    // staging).  The tracer, search and solve of a chunk run on wstream while
-    // the field updates of the previous chunk run on the context's stream.
+    // runs in chunks of steps: two sets, by chunk parity, of the departure
+    // points, stencils and weights of up to ahead_cap steps with their tracer
+    // coefficients (device, and pinned staging).  A chunk's tracer and search
+    // run on sstream, its solve on wstream, while the solve of the chunk
+    // before and the field updates of the one before that run.
     struct AheadSet {
         double *ex = nullptr, *ey = nullptr, *ez = nullptr, *s2 = nullptr, *w = nullptr;
         int32_t *S = nullptr, *cidx = nullptr;
         StepCoef *sc = nullptr, *sc_host = nullptr;
         const StepCoef *sc_mapped = nullptr;  // sc_host's device address
         hipEvent_t staged = nullptr;   // the coefficients' staging has run
+        hipEvent_t searched = nullptr; // the chunk's departure points and stencils are written
         hipEvent_t solved = nullptr;   // the chunk's weights are written
         hipEvent_t applied = nullptr;  // the chunk's field updates have run
         bool used = false;
     };
     int64_t ahead_cap = 0;
     AheadSet aset[2];
-    hipStream_t wstream = nullptr;
+    hipStream_t wstream = nullptr, sstream = nullptr;
     hipEvent_t run_start = nullptr;
+    bool ahead_off = false;  // the chunk sets did not fit: step by step
     // what the debug taps read: the single-step buffers, or after a run of
     // several steps per launch, its last step's slice of an ahead set
     const double *tex = nullptr, *tey = nullptr, *tez = nullptr, *tw = nullptr;
@@ -73,7 +75,7 @@ struct rbfsl_ctx {
     // profiling: per-step events around the four phases (trace, search and
     // solve back to back on one stream, the field update on its own pair)
     bool prof = false;
-    std::vector<hipEvent_t> ev;  // 6 per recorded step
+    std::vector<hipEvent_t> ev;  // 7 per recorded step
     int64_t ev_used = 0, prof_steps = 0;
     std::vector<int64_t> ev_steps;  // steps covered by each recorded group of 6
     double prof_ms[4] = {0, 0, 0, 0};
@@ -273,21 +275,23 @@ int resolve_nlk(int64_t N, int n, int L, int k, int *Lo, int *ko, char *msg, siz
 }
 
 void ahead_free(rbfsl_ctx *c) {
-    if (c->wstream) (void)hipStreamSynchronize(c->wstream);  // nothing of it still reads the sets
+    if (c->sstream) (void)hipStreamSynchronize(c->sstream);  // nothing of them still uses the sets
+    if (c->wstream) (void)hipStreamSynchronize(c->wstream);
     for (rbfsl_ctx::AheadSet &A : c->aset) {
         void *bufs[] = {A.ex, A.ey, A.ez, A.s2, A.w, A.S, A.cidx, A.sc};
         for (void *b : bufs)
             if (b) (void)hipFree(b);
         if (A.sc_host) (void)hipHostFree(A.sc_host);
-        hipEvent_t evs[] = {A.staged, A.solved, A.applied};
+        hipEvent_t evs[] = {A.staged, A.searched, A.solved, A.applied};
         for (hipEvent_t e : evs)
             if (e) (void)hipEventDestroy(e);
         A = rbfsl_ctx::AheadSet{};
     }
     if (c->run_start) (void)hipEventDestroy(c->run_start);
     if (c->wstream) (void)hipStreamDestroy(c->wstream);
+    if (c->sstream) (void)hipStreamDestroy(c->sstream);
     c->run_start = nullptr;
-    c->wstream = nullptr;
+    c->wstream = c->sstream = nullptr;
     c->ahead_cap = 0;
 }
 
@@ -322,14 +326,14 @@ int status_code(const int st[ST_WORDS]) {
     return RBFSL_OK;
 }
 
-// One group of six events per profiled step (or chunk of steps): marks 0..3
-// open the trace, search and solve phases and close the solve, 4 and 5
-// bracket the field update.  prof_group reserves a group (-1 when not
+// One group of seven events per profiled step (or chunk of steps): marks 0, 1
+// open the trace and search phases and 6 closes the search, 2 and 3 bracket
+// the solve, 4 and 5 the field update.  prof_group reserves a group (-1 when not
 // profiling); prof_mark records one of its marks on stream s.
 hipError_t prof_group(rbfsl_ctx *c, int64_t steps, int64_t *g) {
     *g = -1;
     if (!c->prof) return hipSuccess;
-    const int64_t need = c->ev_used + 6;
+    const int64_t need = c->ev_used + 7;
     while ((int64_t)c->ev.size() < need) {
         hipEvent_t e;
         hipError_t r = hipEventCreate(&e);
@@ -337,7 +341,7 @@ hipError_t prof_group(rbfsl_ctx *c, int64_t steps, int64_t *g) {
         c->ev.push_back(e);
     }
     *g = c->ev_used;
-    c->ev_used += 6;
+    c->ev_used += 7;
     c->ev_steps.push_back(steps);
     return hipSuccess;
 }
@@ -348,13 +352,13 @@ hipError_t prof_mark(rbfsl_ctx *c, int64_t g, int mark) { return prof_mark(c, g,
 
 // fold recorded events into the per-phase totals (after a synchronisation)
 void prof_collect(rbfsl_ctx *c) {
-    for (int64_t b = 0; b + 6 <= c->ev_used; b += 6) {
+    for (int64_t b = 0; b + 7 <= c->ev_used; b += 7) {
+        static const int from[4] = {0, 1, 2, 4}, to[4] = {1, 6, 3, 5};
         for (int ph = 0; ph < 4; ++ph) {
             float ms = 0.f;
-            const int64_t i0 = b + ph + (ph == 3);
-            if (hipEventElapsedTime(&ms, c->ev[i0], c->ev[i0 + 1]) == hipSuccess) c->prof_ms[ph] += ms;
+            if (hipEventElapsedTime(&ms, c->ev[b + from[ph]], c->ev[b + to[ph]]) == hipSuccess) c->prof_ms[ph] += ms;
         }
-        const size_t gi = (size_t)(b / 6);
+        const size_t gi = (size_t)(b / 7);
         c->prof_steps += (gi < c->ev_steps.size()) ? c->ev_steps[gi] : 1;
     }
     c->ev_used = 0;
@@ -391,7 +395,7 @@ hipError_t enqueue_step(rbfsl_ctx *c, int64_t m) {
         // coefficients, the partition-of-unity blend
         const PuArgs a = pu_args(c, m);
         if ((e = launch_pu_search(a, c->cgrid, c->stream)) != hipSuccess) return e;
-        if ((e = prof_mark(c, g, 2)) != hipSuccess) return e;
+        if ((e = prof_mark(c, g, 6)) != hipSuccess || (e = prof_mark(c, g, 2)) != hipSuccess) return e;
         if ((e = launch_pu_coef(a, c->stream)) != hipSuccess) return e;
         if ((e = prof_mark(c, g, 3)) != hipSuccess || (e = prof_mark(c, g, 4)) != hipSuccess) return e;
         if ((e = launch_pu_eval(a, c->stream)) != hipSuccess) return e;
@@ -402,7 +406,7 @@ hipError_t enqueue_step(rbfsl_ctx *c, int64_t m) {
     else
         e = launch_knn(c->grid, c->N, c->ex, c->ey, c->ez, c->N, 1, c->cidx, nullptr, nullptr, c->status, m, c->stream);
     if (e != hipSuccess) return e;
-    if ((e = prof_mark(c, g, 2)) != hipSuccess) return e;
+    if ((e = prof_mark(c, g, 6)) != hipSuccess || (e = prof_mark(c, g, 2)) != hipSuccess) return e;
     SolveArgs a{};
     a.nx = c->nx; a.ny = c->ny; a.nz = c->nz; a.N = c->N;
     a.ex = c->ex; a.ey = c->ey; a.ez = c->ez;
@@ -438,23 +442,31 @@ hipError_t enqueue_step(rbfsl_ctx *c, int64_t m) {
 // velocity is prescribed), so K steps' tracer, search and solve run as one
 // launch each, and then the K field updates in step order.  Every step's
 // arithmetic is the step-by-step path's.  A run is cut into about AHEAD_CHUNKS
-// chunks so that the weights of one chunk are computed while the field
-// updates of the one before run.
+// chunks so that the search of one chunk, the solve of the one before and the
+// field updates of the one before that overlap.  Problems too large for two
+// steps per launch (N > AHEAD_STENCILS / 2) go step by step: with chunks of
+// one step, the next step's search running beside the solve slowed it by more
+// than the search and update time it hid (N = 655,362, n = 120: 548.8 against
+// 545.5 ms per step).
 constexpr int64_t AHEAD_STENCILS = 131072;  // stencils per launch at most
 constexpr int64_t AHEAD_MAX = 128;
 constexpr int64_t AHEAD_CHUNKS = 4;
 
-// the most steps per launch this context takes (1: step by step only)
+// the most steps per chunk this context takes
 int64_t ahead_max(const rbfsl_ctx *c) {
-    if (c->mode == RBFSL_STENCIL_PU || c->cached) return 1;
     const int64_t K = std::min(AHEAD_MAX, AHEAD_STENCILS / c->N);
-    return (K < 2) ? 1 : K;
+    return (K < 1) ? 1 : K;
+}
+
+// runs of this many steps go in chunks (not the cached, RBF-PU or single-step
+// forms, nor problems of more than AHEAD_STENCILS / 2 nodes)
+bool chunked(const rbfsl_ctx *c, int64_t nsteps) {
+    return c->mode != RBFSL_STENCIL_PU && !c->cached && !c->ahead_off && nsteps >= 2 && ahead_max(c) >= 2;
 }
 
 int64_t ahead_steps(const rbfsl_ctx *c, int64_t nsteps) {
-    const int64_t Km = ahead_max(c);
-    if (Km < 2 || nsteps < 2) return 1;
-    return std::min(Km, std::max<int64_t>(2, (nsteps + AHEAD_CHUNKS - 1) / AHEAD_CHUNKS));
+    if (!chunked(c, nsteps)) return 1;
+    return std::min(ahead_max(c), std::max<int64_t>(2, (nsteps + AHEAD_CHUNKS - 1) / AHEAD_CHUNKS));
 }
 
 // both sets at the context's largest chunk, once (a run never reallocates)
@@ -462,6 +474,7 @@ hipError_t ahead_alloc(rbfsl_ctx *c) {
     if (c->ahead_cap > 0) return hipSuccess;
     const int64_t K = ahead_max(c), KN = K * c->N;
     hipError_t e = hipStreamCreateWithFlags(&c->wstream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->sstream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->run_start, hipEventDisableTiming);
 #define ALLOC(ptr, bytes) if (e == hipSuccess) e = hipMalloc(&(ptr), (bytes))
 #define EVENT(ev) if (e == hipSuccess) e = hipEventCreateWithFlags(&(ev), hipEventDisableTiming)
@@ -480,6 +493,7 @@ hipError_t ahead_alloc(rbfsl_ctx *c) {
         if (e == hipSuccess) e = hipHostMalloc((void **)&A.sc_host, sizeof(StepCoef) * K, hipHostMallocMapped);
         if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&A.sc_mapped, A.sc_host, 0);
         EVENT(A.staged);
+        EVENT(A.searched);
         EVENT(A.solved);
         EVENT(A.applied);
     }
@@ -508,32 +522,36 @@ void taps_ahead(rbfsl_ctx *c, int cb, int64_t s) {
     }
 }
 
-// The departure points, stencils and weights of steps m .. m + K - 1 into set
-// cb, on wstream, after the field updates that last read the set.
+// The departure points and stencils of steps m .. m + K - 1 into set cb on
+// sstream, after the field updates that last read the set; their weights on
+// wstream, after that search.
 hipError_t enqueue_weights(rbfsl_ctx *c, int64_t m, int K, int cb, int64_t g) {
     rbfsl_ctx::AheadSet &A = c->aset[cb];
-    const hipStream_t ws = c->wstream;
+    const hipStream_t ss = c->sstream, ws = c->wstream;
     hipError_t e;
     if (A.used && (e = hipEventSynchronize(A.staged)) != hipSuccess) return e;
     for (int s = 0; s < K; ++s) A.sc_host[s] = make_step_coef(c->p, m + s);
-    if (A.used && (e = hipStreamWaitEvent(ws, A.applied, 0)) != hipSuccess) return e;
+    if (A.used && (e = hipStreamWaitEvent(ss, A.applied, 0)) != hipSuccess) return e;
     static_assert(sizeof(StepCoef) % sizeof(uint64_t) == 0, "StepCoef is staged as 64-bit words");
     const int64_t nwords = (int64_t)(sizeof(StepCoef) / sizeof(uint64_t)) * K;
-    hipLaunchKernelGGL(k_stage_words, dim3((unsigned)((nwords + 255) / 256)), dim3(256), 0, ws,
+    hipLaunchKernelGGL(k_stage_words, dim3((unsigned)((nwords + 255) / 256)), dim3(256), 0, ss,
                        (const uint64_t *)A.sc_mapped, (uint64_t *)A.sc, nwords);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = hipEventRecord(A.staged, ws)) != hipSuccess) return e;
+    if ((e = hipEventRecord(A.staged, ss)) != hipSuccess) return e;
     A.used = true;
     const int64_t N = c->N, KN = (int64_t)K * N;
-    if ((e = prof_mark(c, g, 0, ws)) != hipSuccess) return e;
-    if ((e = launch_trace_steps(c->nx, c->ny, c->nz, N, A.sc, K, A.ex, A.ey, A.ez, c->status, m, ws)) != hipSuccess)
+    if ((e = prof_mark(c, g, 0, ss)) != hipSuccess) return e;
+    if ((e = launch_trace_steps(c->nx, c->ny, c->nz, N, A.sc, K, A.ex, A.ey, A.ez, c->status, m, ss)) != hipSuccess)
         return e;
-    if ((e = prof_mark(c, g, 1, ws)) != hipSuccess) return e;
+    if ((e = prof_mark(c, g, 1, ss)) != hipSuccess) return e;
     if (c->mode == 0)
-        e = launch_knn(c->grid, N, A.ex, A.ey, A.ez, KN, c->n, A.S, nullptr, A.s2, c->status, m, ws, N);
+        e = launch_knn(c->grid, N, A.ex, A.ey, A.ez, KN, c->n, A.S, nullptr, A.s2, c->status, m, ss, N);
     else
-        e = launch_knn(c->grid, N, A.ex, A.ey, A.ez, KN, 1, A.cidx, nullptr, nullptr, c->status, m, ws, N);
+        e = launch_knn(c->grid, N, A.ex, A.ey, A.ez, KN, 1, A.cidx, nullptr, nullptr, c->status, m, ss, N);
     if (e != hipSuccess) return e;
+    if ((e = prof_mark(c, g, 6, ss)) != hipSuccess) return e;
+    if ((e = hipEventRecord(A.searched, ss)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(ws, A.searched, 0)) != hipSuccess) return e;
     if ((e = prof_mark(c, g, 2, ws)) != hipSuccess) return e;
     SolveArgs a{};
     a.nx = c->nx; a.ny = c->ny; a.nz = c->nz; a.N = N;
@@ -898,15 +916,24 @@ int rbfsl_run(rbfsl_ctx *c, int64_t nsteps) {
     HIP_TRY(c, launch_status_reset(c->status, c->stream));
     const int64_t m0 = c->step;
     const int cur0 = c->cur;
-    const int64_t K = ahead_steps(c, nsteps);
-    if (K > 1) {
-        HIP_TRY(c, ahead_alloc(c));
-        // the tracer, search and solve stream starts after the status reset
+    if (chunked(c, nsteps) && c->ahead_cap == 0) {
+        const hipError_t ea = ahead_alloc(c);
+        if (ea == hipErrorOutOfMemory) {  // the chunk sets do not fit: step by step from now on
+            (void)hipGetLastError();
+            c->ahead_off = true;
+        } else if (ea != hipSuccess) {
+            return fail(c, RBFSL_E_DEVICE, "chunk buffers: %s", hipGetErrorString(ea));
+        }
+    }
+    if (chunked(c, nsteps)) {
+        const int64_t K = ahead_steps(c, nsteps);
+        // the search stream starts after the status reset
         HIP_TRY(c, hipEventRecord(c->run_start, c->stream));
-        HIP_TRY(c, hipStreamWaitEvent(c->wstream, c->run_start, 0));
+        HIP_TRY(c, hipStreamWaitEvent(c->sstream, c->run_start, 0));
         int64_t m = m0;
         const hipError_t e = enqueue_chunks(c, m0, nsteps, K, cur0, &m);
         if (e != hipSuccess) {
+            (void)hipStreamSynchronize(c->sstream);
             (void)hipStreamSynchronize(c->wstream);
             (void)hipStreamSynchronize(c->stream);
             c->cur = cur0;

@@ -1,6 +1,8 @@
-"""Runs of small problems take several steps per launch (the departure points,
-stencils and weights of a step do not depend on the transported field): a run
-of m steps must give, bit for bit, what m single steps give, in both stencil
+"""Runs go in chunks of steps whose searches, solves and field updates overlap
+on three streams, small problems with several steps per launch (the
+departure points, stencils and weights of a step do not depend on the
+transported field): a run of m steps must give, bit for bit, what m single
+steps give, in both stencil
 modes, with several tracers, across chunk boundaries, with the debug taps
 showing the last step.  The single-step path is itself checked against the oracle by
 the parity tests (and the 128-step run of the N=1,024 workload against the
@@ -47,6 +49,8 @@ CASES = [
     (1024, 31, 3, 2, 0, 8, 24),
     (5000, 39, 4, 2, 0, 1, 30),    # chunks of 8, 8, 8, 3, 3 steps
     (2562, 56, 4, 2, 1, 2, 60),
+    (70000, 31, 3, 2, 0, 1, 5),    # N > 65,536: step by step
+    (70000, 56, 4, 2, 1, 2, 4),
 ]
 
 
