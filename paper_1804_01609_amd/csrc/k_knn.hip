@@ -4,8 +4,6 @@
 
 namespace rbfsl {
 
-constexpr int KNN_SMALL_N = 256;
-
 template <int CAP>
 __global__ void __launch_bounds__(64) k_knn(GridView g, const double *__restrict__ qx,
                                             const double *__restrict__ qy,

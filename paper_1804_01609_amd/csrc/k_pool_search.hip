@@ -1,19 +1,60 @@
-// Search pass of a pooled step: for every node of every run with steps left,
-// the departure point (RK4, Section 3.2) and the exact n-nearest-node stencil
-// of it (Sections 2.2 and 3.3.2), written to the run's xi / S / s2 buffers.
-// One wave per node, grid-stride over the search queue (items = nodes); the
-// search does not depend on q, so it runs ahead of the solves at the high
-// occupancy a latency-bound search needs.
+// Trace and search passes of a pooled step: for every node of every run with
+// steps left, the departure point (RK4, Section 3.2; one thread per node)
+// and then the exact n-nearest-node stencil of it (Sections 2.2 and 3.3.2;
+// one wave per node), written to the run's xi / S / s2 buffers, grid-stride
+// over the search queue (items = nodes).  Neither depends on q, so they run
+// ahead of the solves; as two kernels, the search keeps the registers of the
+// search alone and the occupancy a latency-bound search needs (with the
+// tracer inlined it took twice the registers and half the waves).
 #include "k_knn.h"
 #include "k_trace.h"
 #include "pool_impl.h"
 
 namespace rbfsl {
 
-constexpr int POOL_KNN_CAP = 512;
+// The candidate store of the single-run search for the same n: a quarter of
+// the full store up to n = KNN_SMALL_N / 2, else half (the pool's systems hold
+// n < MAX_SYSTEM <= KNN_SMALL_N), so that both paths sort the same number of
+// keys and fail on the same node clusters.  One LDS area serves both sizes.
+static_assert(MAX_SYSTEM <= KNN_SMALL_N, "pooled stencils fit the half-size store");
+union PoolKnnSmem {
+    KnnSmem<KNN_CAP / 4> q;
+    KnnSmem<KNN_CAP / 2> h;
+};
+
+// the segment of queue item `item`: the last with item0 <= item
+__device__ __forceinline__ int pool_segment(const PoolQueue *Q, int64_t item) {
+    int l = 0, hi = Q->nseg - 1;
+    while (l < hi) {
+        const int mid = (l + hi + 1) >> 1;
+        if (Q->seg[mid].item0 <= item) l = mid;
+        else hi = mid - 1;
+    }
+    return l;
+}
+
+__global__ void __launch_bounds__(256) k_pool_trace(PoolArgs P) {
+    const PoolQueue *Q = P.queue;
+    const int64_t nitems = Q->nitems;
+    for (int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; item < nitems;
+         item += (int64_t)gridDim.x * blockDim.x) {
+        const PoolSeg &sg = Q->seg[pool_segment(Q, item)];
+        const int64_t j = item - sg.item0;
+        const PoolRunDev &r = P.runs[sg.slot];
+        const int64_t step = P.state[sg.slot].step;
+        if (step >= r.nsteps || r.status[ST_FAILSTEP] <= step) continue;
+        const int64_t N = r.N;
+        const double x[3] = {r.nx[j], r.ny[j], r.nz[j]};
+        double xi[3];
+        trace_point(r.coef[step], x, xi);
+        r.xi[j] = xi[0];
+        r.xi[N + j] = xi[1];
+        r.xi[2 * N + j] = xi[2];
+    }
+}
 
 __global__ void __launch_bounds__(64) k_pool_search(PoolArgs P) {
-    __shared__ KnnSmem<POOL_KNN_CAP> sh;
+    __shared__ PoolKnnSmem sh;
     const int lane = threadIdx.x;
     const PoolQueue *Q = P.queue;
     const int64_t nitems = Q->nitems;
@@ -22,13 +63,7 @@ __global__ void __launch_bounds__(64) k_pool_search(PoolArgs P) {
     int64_t s_lo = 0, s_hi = 0;  // item range of segment lo, searched only when an item leaves it
     for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
         if (!(item >= s_lo && item < s_hi)) {
-            int l = 0, hi = nseg - 1;  // last segment with item0 <= item
-            while (l < hi) {
-                const int mid = (l + hi + 1) >> 1;
-                if (Q->seg[mid].item0 <= item) l = mid;
-                else hi = mid - 1;
-            }
-            lo = l;
+            lo = pool_segment(Q, item);
             s_lo = Q->seg[lo].item0;
             s_hi = (lo + 1 < nseg) ? Q->seg[lo + 1].item0 : nitems;
         }
@@ -38,11 +73,17 @@ __global__ void __launch_bounds__(64) k_pool_search(PoolArgs P) {
         const int64_t step = P.state[slot].step;
         if (step >= r.nsteps || r.status[ST_FAILSTEP] <= step) continue;
         const int64_t N = r.N;
-        const double x[3] = {r.nx[j], r.ny[j], r.nz[j]};
-        double xi[3];
-        trace_point(r.coef[step], x, xi);
+        const double xi[3] = {r.xi[j], r.xi[N + j], r.xi[2 * N + j]};
         const GridView gv{r.G, r.invh, r.cell_start, r.sx, r.sy, r.sz, r.perm};
-        if (!knn_wave<POOL_KNN_CAP>(sh, lane, gv, xi[0], xi[1], xi[2], r.n, r.R0)) {
+        // the lane index, opaque per node: otherwise the compiler hoists the
+        // search's lane-derived LDS addresses out of the node loop and keeps
+        // them live (twice the registers of the single-run search)
+        int ln = lane;
+        __asm__ volatile("" : "+v"(ln));
+        const bool quarter = r.n <= KNN_SMALL_N / 2;
+        const bool found = quarter ? knn_wave<KNN_CAP / 4>(sh.q, ln, gv, xi[0], xi[1], xi[2], r.n, r.R0)
+                                   : knn_wave<KNN_CAP / 2>(sh.h, ln, gv, xi[0], xi[1], xi[2], r.n, r.R0);
+        if (!found) {
             if (lane == 0) {
                 atomicAdd(&r.status[ST_SEARCH], 1);
                 atomicMin(&r.status[ST_FAILSTEP], (int)step);
@@ -50,18 +91,18 @@ __global__ void __launch_bounds__(64) k_pool_search(PoolArgs P) {
             continue;
         }
         int32_t *Sj = r.S + j * r.n;
-        for (int a = lane; a < r.n; a += 64) Sj[a] = sh.ki[a];
-        if (lane == 0) {
-            r.xi[j] = xi[0];
-            r.xi[N + j] = xi[1];
-            r.xi[2 * N + j] = xi[2];
-            r.s2[j] = sh.kd[r.n - 1];
-        }
+        const int *ki = quarter ? sh.q.ki : sh.h.ki;
+        const double *kd = quarter ? sh.q.kd : sh.h.kd;
+        for (int a = lane; a < r.n; a += 64) Sj[a] = ki[a];
+        if (lane == 0) r.s2[j] = kd[r.n - 1];
         wave_lds_sync();  // the stencil is read before the next search reuses the buffers
     }
 }
 
-hipError_t pool_launch_search(const PoolArgs &a, int blocks, hipStream_t s) {
+hipError_t pool_launch_search(const PoolArgs &a, int blocks, int trace_blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_pool_trace, dim3((unsigned)trace_blocks), dim3(256), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_pool_search, dim3((unsigned)blocks), dim3(64), 0, s, a);
     return hipGetLastError();
 }

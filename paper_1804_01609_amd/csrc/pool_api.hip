@@ -374,7 +374,9 @@ hipError_t enqueue_step_kernels(rbfsl_pool *pl, bool commit) {
     hipLaunchKernelGGL(k_pool_reset, dim3(1), dim3(64), 0, pl->main, qs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if ((e = pool_launch_search(family_args(pl, POOL_FAMILIES), pl->search_blocks, pl->main)) != hipSuccess) return e;
+    if ((e = pool_launch_search(family_args(pl, POOL_FAMILIES), pl->search_blocks, 8 * pl->ncu, pl->main)) !=
+        hipSuccess)
+        return e;
     if ((e = hipEventRecord(pl->fork, pl->main)) != hipSuccess) return e;
     for (int f = 1; f < POOL_FAMILIES; ++f)
         if ((e = hipStreamWaitEvent(pl->side[f - 1], pl->fork, 0)) != hipSuccess) return e;

@@ -68,9 +68,11 @@ struct PoolArgs {
     PoolQueue *queue;
 };
 
-// The stencil search of a step, for every node of every run (queue items =
-// nodes): one wave per node, grid-stride over the queue.
-hipError_t pool_launch_search(const PoolArgs &a, int blocks, hipStream_t s);
+// The tracer and stencil search of a step, for every node of every run
+// (queue items = nodes): the departure points with trace_blocks workgroups of
+// 256 threads, one thread per node, then the stencils with `blocks`
+// workgroups of one wave, one wave per node; both grid-stride over the queue.
+hipError_t pool_launch_search(const PoolArgs &a, int blocks, int trace_blocks, hipStream_t s);
 int pool_search_blocks_per_cu();
 
 // Kernel families, by waves per workgroup: 4 (systems up to 128 unknowns,

@@ -62,8 +62,10 @@ struct Grid {
 enum { ST_SINGULAR = 0, ST_NONFINITE = 1, ST_SEARCH = 2, ST_FAILSTEP = 3, ST_WORDS = 4 };
 constexpr int NO_FAIL = 0x7fffffff;
 
-// kNN capacity: candidates kept per query inside the search ball.
+// kNN capacity: candidates kept per query inside the search ball; searches
+// for n <= KNN_SMALL_N / 2 keep a quarter of it, for n <= KNN_SMALL_N half.
 constexpr int KNN_CAP = 1024;
+constexpr int KNN_SMALL_N = 256;
 constexpr int MAX_SYSTEM = 192;
 
 // ---- launchers (return hipSuccess or the launch error) ----
