@@ -1,11 +1,12 @@
 // Trace and search passes of a pooled step: for every node of every run with
 // steps left, the departure point (RK4, Section 3.2; one thread per node)
 // and then the exact n-nearest-node stencil of it (Sections 2.2 and 3.3.2;
-// one wave per node), written to the run's xi / S / s2 buffers, grid-stride
-// over the search queue (items = nodes).  Neither depends on q, so they run
-// ahead of the solves; as two kernels, the search keeps the registers of the
-// search alone and the occupancy a latency-bound search needs (with the
-// tracer inlined it took twice the registers and half the waves).
+// one wave per node), written to the run's xi / S / s2 buffers, for every item
+// of the search queue (items = nodes), launched outside the step's graph
+// with one thread or one wave per node.  Neither depends on q, so they run
+// ahead of the solves; as two plain kernels (no tracer inlined, no loop over
+// nodes) the search keeps the registers of the search alone and the
+// occupancy a latency-bound search needs.
 #include "k_knn.h"
 #include "k_trace.h"
 #include "pool_impl.h"
@@ -33,86 +34,65 @@ __device__ __forceinline__ int pool_segment(const PoolQueue *Q, int64_t item) {
     return l;
 }
 
+// one thread per queue item (node)
 __global__ void __launch_bounds__(256) k_pool_trace(PoolArgs P) {
     const PoolQueue *Q = P.queue;
-    const int64_t nitems = Q->nitems;
-    for (int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; item < nitems;
-         item += (int64_t)gridDim.x * blockDim.x) {
-        const PoolSeg &sg = Q->seg[pool_segment(Q, item)];
-        const int64_t j = item - sg.item0;
-        const PoolRunDev &r = P.runs[sg.slot];
-        const int64_t step = P.state[sg.slot].step;
-        if (step >= r.nsteps || r.status[ST_FAILSTEP] <= step) continue;
-        const int64_t N = r.N;
-        const double x[3] = {r.nx[j], r.ny[j], r.nz[j]};
-        double xi[3];
-        trace_point(r.coef[step], x, xi);
-        r.xi[j] = xi[0];
-        r.xi[N + j] = xi[1];
-        r.xi[2 * N + j] = xi[2];
-    }
+    const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (item >= Q->nitems) return;
+    const PoolSeg &sg = Q->seg[pool_segment(Q, item)];
+    const int64_t j = item - sg.item0;
+    const PoolRunDev &r = P.runs[sg.slot];
+    const int64_t step = P.state[sg.slot].step;
+    if (step >= r.nsteps || r.status[ST_FAILSTEP] <= step) return;
+    const int64_t N = r.N;
+    const double x[3] = {r.nx[j], r.ny[j], r.nz[j]};
+    double xi[3];
+    trace_point(r.coef[step], x, xi);
+    r.xi[j] = xi[0];
+    r.xi[N + j] = xi[1];
+    r.xi[2 * N + j] = xi[2];
 }
 
+// one wave per queue item (node)
 __global__ void __launch_bounds__(64) k_pool_search(PoolArgs P) {
     __shared__ PoolKnnSmem sh;
     const int lane = threadIdx.x;
     const PoolQueue *Q = P.queue;
-    const int64_t nitems = Q->nitems;
-    const int nseg = Q->nseg;
-    int lo = 0;
-    int64_t s_lo = 0, s_hi = 0;  // item range of segment lo, searched only when an item leaves it
-    for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
-        if (!(item >= s_lo && item < s_hi)) {
-            lo = pool_segment(Q, item);
-            s_lo = Q->seg[lo].item0;
-            s_hi = (lo + 1 < nseg) ? Q->seg[lo + 1].item0 : nitems;
+    const int64_t item = blockIdx.x;
+    if (item >= Q->nitems) return;
+    const int lo = pool_segment(Q, item);
+    const int slot = __builtin_amdgcn_readfirstlane(Q->seg[lo].slot);
+    const int64_t j = item - Q->seg[lo].item0;
+    const PoolRunDev &r = P.runs[slot];
+    const int64_t step = P.state[slot].step;
+    if (step >= r.nsteps || r.status[ST_FAILSTEP] <= step) return;
+    const int64_t N = r.N;
+    const double xi[3] = {r.xi[j], r.xi[N + j], r.xi[2 * N + j]};
+    const GridView gv{r.G, r.invh, r.cell_start, r.sx, r.sy, r.sz, r.perm};
+    const bool quarter = r.n <= KNN_SMALL_N / 2;
+    const bool found = quarter ? knn_wave<KNN_CAP / 4>(sh.q, lane, gv, xi[0], xi[1], xi[2], r.n, r.R0)
+                               : knn_wave<KNN_CAP / 2>(sh.h, lane, gv, xi[0], xi[1], xi[2], r.n, r.R0);
+    if (!found) {
+        if (lane == 0) {
+            atomicAdd(&r.status[ST_SEARCH], 1);
+            atomicMin(&r.status[ST_FAILSTEP], (int)step);
         }
-        const int slot = __builtin_amdgcn_readfirstlane(Q->seg[lo].slot);
-        const int64_t j = item - s_lo;
-        const PoolRunDev &r = P.runs[slot];
-        const int64_t step = P.state[slot].step;
-        if (step >= r.nsteps || r.status[ST_FAILSTEP] <= step) continue;
-        const int64_t N = r.N;
-        const double xi[3] = {r.xi[j], r.xi[N + j], r.xi[2 * N + j]};
-        const GridView gv{r.G, r.invh, r.cell_start, r.sx, r.sy, r.sz, r.perm};
-        // the lane index, opaque per node: otherwise the compiler hoists the
-        // search's lane-derived LDS addresses out of the node loop and keeps
-        // them live (twice the registers of the single-run search)
-        int ln = lane;
-        __asm__ volatile("" : "+v"(ln));
-        const bool quarter = r.n <= KNN_SMALL_N / 2;
-        const bool found = quarter ? knn_wave<KNN_CAP / 4>(sh.q, ln, gv, xi[0], xi[1], xi[2], r.n, r.R0)
-                                   : knn_wave<KNN_CAP / 2>(sh.h, ln, gv, xi[0], xi[1], xi[2], r.n, r.R0);
-        if (!found) {
-            if (lane == 0) {
-                atomicAdd(&r.status[ST_SEARCH], 1);
-                atomicMin(&r.status[ST_FAILSTEP], (int)step);
-            }
-            continue;
-        }
-        int32_t *Sj = r.S + j * r.n;
-        const int *ki = quarter ? sh.q.ki : sh.h.ki;
-        const double *kd = quarter ? sh.q.kd : sh.h.kd;
-        for (int a = lane; a < r.n; a += 64) Sj[a] = ki[a];
-        if (lane == 0) r.s2[j] = kd[r.n - 1];
-        wave_lds_sync();  // the stencil is read before the next search reuses the buffers
+        return;
     }
+    const int *ki = quarter ? sh.q.ki : sh.h.ki;
+    const double *kd = quarter ? sh.q.kd : sh.h.kd;
+    int32_t *Sj = r.S + j * r.n;
+    for (int a = lane; a < r.n; a += 64) Sj[a] = ki[a];
+    if (lane == 0) r.s2[j] = kd[r.n - 1];
 }
 
-hipError_t pool_launch_search(const PoolArgs &a, int blocks, int trace_blocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_pool_trace, dim3((unsigned)trace_blocks), dim3(256), 0, s, a);
+hipError_t pool_launch_search(const PoolArgs &a, int64_t items, hipStream_t s) {
+    if (items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pool_trace, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pool_search, dim3((unsigned)blocks), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_pool_search, dim3((unsigned)items), dim3(64), 0, s, a);
     return hipGetLastError();
-}
-
-int pool_search_blocks_per_cu() {
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k_pool_search), 64, 0) !=
-        hipSuccess)
-        return 0;
-    return nb;
 }
 
 }  // namespace rbfsl

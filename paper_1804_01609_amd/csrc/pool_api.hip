@@ -241,7 +241,7 @@ struct rbfsl_pool {
     const PoolQueue *m_queue[POOL_FAMILIES + 1][2] = {};
     const int *m_on[2] = {};
     hipEvent_t tev[2] = {};                            // the staging of ring slot r has been read
-    int search_blocks = 0;
+    int64_t search_items = 0;  // nodes in the search queue
     int qring = 0;
     bool dirty = true;
     int blocks[POOL_FAMILIES] = {};
@@ -341,6 +341,7 @@ int upload_tables(rbfsl_pool *pl) {
         h->pad = 0;
         h->next = 0;
         if (!search) pl->items_last[f] = item;
+        else pl->search_items = item;
         static_assert(offsetof(PoolQueue, seg) % 8 == 0 && sizeof(PoolSeg) % 8 == 0, "staged as 64-bit words");
         L.src[f] = reinterpret_cast<const uint64_t *>(pl->m_queue[f][ring]);
         L.dst[f] = reinterpret_cast<uint64_t *>(pl->d_queue[f]);
@@ -366,17 +367,20 @@ PoolArgs family_args(rbfsl_pool *pl, int f) {
     return a;
 }
 
-// one step: reset the claim counters, the search pass, the solve families
-// (all but the first on side streams, joined back), commit
+// the trace and search passes of a step, sized by the current search queue
+// (outside the captured graph, whose launch sizes are fixed)
+hipError_t enqueue_search(rbfsl_pool *pl) {
+    return pool_launch_search(family_args(pl, POOL_FAMILIES), pl->search_items, pl->main);
+}
+
+// the rest of a step: reset the claim counters, the solve families (all but
+// the first on side streams, joined back), commit
 hipError_t enqueue_step_kernels(rbfsl_pool *pl, bool commit) {
     QueueSet qs;
     for (int f = 0; f < POOL_FAMILIES; ++f) qs.q[f] = pl->d_queue[f];
     hipLaunchKernelGGL(k_pool_reset, dim3(1), dim3(64), 0, pl->main, qs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if ((e = pool_launch_search(family_args(pl, POOL_FAMILIES), pl->search_blocks, 8 * pl->ncu, pl->main)) !=
-        hipSuccess)
-        return e;
     if ((e = hipEventRecord(pl->fork, pl->main)) != hipSuccess) return e;
     for (int f = 1; f < POOL_FAMILIES; ++f)
         if ((e = hipStreamWaitEvent(pl->side[f - 1], pl->fork, 0)) != hipSuccess) return e;
@@ -404,6 +408,7 @@ int launch_one_step(rbfsl_pool *pl) {
         int r = upload_tables(pl);
         if (r != RBFSL_OK) return r;
     }
+    PHIP(pl, enqueue_search(pl));
     if (pl->use_graph) {
         if (!pl->exec) {
             PHIP(pl, hipStreamBeginCapture(pl->main, hipStreamCaptureModeThreadLocal));
@@ -692,11 +697,6 @@ int rbfsl_pool_create(const rbfsl_pool_config *cfg, rbfsl_pool **out) {
         if (bpc < 1) e = hipErrorInvalidConfiguration;
         pl->blocks[f] = bpc * pl->ncu;
     }
-    if (e == hipSuccess) {
-        const int bpc = pool_search_blocks_per_cu();
-        if (bpc < 1) e = hipErrorInvalidConfiguration;
-        pl->search_blocks = bpc * pl->ncu;
-    }
     if (e != hipSuccess) {
         const int code = (e == hipErrorOutOfMemory) ? RBFSL_E_NOMEM : RBFSL_E_DEVICE;
         pool_free(pl);
@@ -847,9 +847,13 @@ int rbfsl_pool_tune(rbfsl_pool *pl, int32_t trials, rbfsl_tune_result *res, int3
             float ms = 0.f;
             hipError_t e = hipSuccess;
             if (rc == RBFSL_OK) {
-                e = enqueue_step_kernels(pl, false);  // warm-up
+                e = enqueue_search(pl);  // warm-up
+                if (e == hipSuccess) e = enqueue_step_kernels(pl, false);
                 if (e == hipSuccess) e = hipEventRecord(e0, pl->main);
-                for (int t = 0; t < trials && e == hipSuccess; ++t) e = enqueue_step_kernels(pl, false);
+                for (int t = 0; t < trials && e == hipSuccess; ++t) {
+                    e = enqueue_search(pl);
+                    if (e == hipSuccess) e = enqueue_step_kernels(pl, false);
+                }
                 if (e == hipSuccess) e = hipEventRecord(e1, pl->main);
                 if (e == hipSuccess) e = hipEventSynchronize(e1);
                 if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);

@@ -69,11 +69,9 @@ struct PoolArgs {
 };
 
 // The tracer and stencil search of a step, for every node of every run
-// (queue items = nodes): the departure points with trace_blocks workgroups of
-// 256 threads, one thread per node, then the stencils with `blocks`
-// workgroups of one wave, one wave per node; both grid-stride over the queue.
-hipError_t pool_launch_search(const PoolArgs &a, int blocks, int trace_blocks, hipStream_t s);
-int pool_search_blocks_per_cu();
+// (queue items = nodes; `items` is the search queue's item count): the
+// departure points, one thread per node, then the stencils, one wave per node.
+hipError_t pool_launch_search(const PoolArgs &a, int64_t items, hipStream_t s);
 
 // Kernel families, by waves per workgroup: 4 (systems up to 128 unknowns,
 // one, two or four waves per stencil), 8 (up to 192 unknowns), 3 (up to 90
