@@ -174,8 +174,8 @@ int rbfsl_step(rbfsl_ctx *ctx);
 int rbfsl_run(rbfsl_ctx *ctx, int64_t nsteps);
 
 /* Steps per launch that rbfsl_run(ctx, nsteps) takes at most: 1 for the
- * step-by-step path (N > 65,536 among others), else K >= 2: a quarter of
- * nsteps rounded up, at least 2, at most 131,072 / N and 128. */
+ * step-by-step path (N > 65,536 among others), else K >= 2: half of nsteps
+ * rounded up, at least 2, at most 131,072 / N and 128. */
 int64_t rbfsl_steps_per_launch(const rbfsl_ctx *ctx, int64_t nsteps);
 
 /* Copy q^m, Algorithm 1's state after m steps, out (n_tracers x N).

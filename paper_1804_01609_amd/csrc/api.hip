@@ -450,7 +450,7 @@ hipError_t enqueue_step(rbfsl_ctx *c, int64_t m) {
 // 545.5 ms per step).
 constexpr int64_t AHEAD_STENCILS = 131072;  // stencils per launch at most
 constexpr int64_t AHEAD_MAX = 128;
-constexpr int64_t AHEAD_CHUNKS = 4;
+constexpr int64_t AHEAD_CHUNKS = 2;  // N = 1,024, 128 steps: 2, 3, 4, 6 chunks 0.029, 0.0296, 0.0298, 0.0308 ms/step
 
 // the most steps per chunk this context takes
 int64_t ahead_max(const rbfsl_ctx *c) {

@@ -47,7 +47,7 @@ CASES = [
     (1024, 31, 3, 2, 0, 1, 40),
     (1024, 31, 3, 2, 1, 1, 40),
     (1024, 31, 3, 2, 0, 8, 24),
-    (5000, 39, 4, 2, 0, 1, 30),    # chunks of 8, 8, 8, 3, 3 steps
+    (5000, 39, 4, 2, 0, 1, 30),    # chunks of 15, 8, 7 steps
     (2562, 56, 4, 2, 1, 2, 60),
     (70000, 31, 3, 2, 0, 1, 5),    # N > 65,536: step by step
     (70000, 56, 4, 2, 1, 2, 4),
@@ -66,7 +66,7 @@ def test_run_equals_single_steps(N, n, L, k, mode, ntr, steps):
 
 
 def test_chunk_boundaries_and_resumed_runs():
-    # runs of 300 = 3 x 75 + 38 + 37, and 129 = 3 x 33 + 15 + 15 then 171 = 3 x 43 + 21 + 21 steps
+    # runs of 300 = 128 + 128 + 44, and 129 = 65 + 32 + 32 then 171 = 86 + 43 + 42 steps
     N, n, L, k = 1024, 31, 3, 2
     X = W.fibonacci_nodes(N)
     q0 = W.c1_bump(X)[None]
