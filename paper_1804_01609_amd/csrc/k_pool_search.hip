@@ -88,6 +88,7 @@ __global__ void __launch_bounds__(64) k_pool_search(PoolArgs P) {
 
 hipError_t pool_launch_search(const PoolArgs &a, int64_t items, hipStream_t s) {
     if (items <= 0) return hipSuccess;
+    if (items > 0x7fffffffLL) return hipErrorInvalidConfiguration;  // one workgroup per node
     hipLaunchKernelGGL(k_pool_trace, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
