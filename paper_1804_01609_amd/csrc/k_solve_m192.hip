@@ -1,5 +1,5 @@
 // Solver instantiation for systems of size M <= 192: 16 waves per stencil,
-// 3 row slots per lane, 3 blocks of 4 column slots per wave (111 VGPRs, 4
+// 3 row slots per lane, 3 blocks of 4 column slots per wave (110 VGPRs, 4
 // waves per SIMD: the pivot-row broadcasts by readlane cost each wave ~16
 // cycles of latency, hidden only when several waves share a SIMD); LDS base
 // opaque to the compiler (no scratch spills).  The factor-only kernel keeps 8
